@@ -1,0 +1,168 @@
+"""Throughput of the two-component lattice Boltzmann hot path on one MI355X.
+
+Workload: the 128^3 droplet box (R = 16, FP32 populations) driven through its
+ghost nodes by a seeded Ornstein-Uhlenbeck velocity-gradient history (synthetic
+stand-in for the turbulence-simulation gradients of Sec. 3).  One benchmark
+"step" is one sample period of 50 lattice steps — 50 fused stream-collide
+launches — followed by the droplet inertia-tensor moments of that sample (FP64
+reduction into a device time series).  --steps 400 (default) times the full
+20000-step run.
+
+Prints one JSON line with MLUPS (one update = both components at one node),
+the roofline of the step kernel (algorithmic bytes per launch over its average
+launch duration, from HIP events on the library's stream) and the FP64 CPU
+oracle timed on a bounded sample of the same box on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+STRIDE = 50
+
+
+def step_kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("step_kernel.hpp", "lattice.hpp"):
+        with open(os.path.join(ROOT, "paper_2112_09972_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_step_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != step_kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(case, seconds: float = 15.0):
+    """The FP64 oracle on the same box and drive, timed on the host cores."""
+    import oracle
+    o = oracle.Oracle(case.n, case.n, case.n, periodic=False, tau=(case.tau, case.tau), g=wl.G_AB,
+                      rho_b=case.rho_b)
+    tab = case.tables[0]
+    o.init_droplet(o.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
+    o.step(tab[0])  # warm-up (page-in, thread start)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.step(tab[1 + steps])
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 200:
+            break
+    return {"value": round(case.n ** 3 * steps / el / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d lattice steps of the %d^3 FP64 droplet box (steps 1..%d of the same OU drive), %.1f s"
+                      % (steps, case.n, steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400, help="timed samples of 50 lattice steps")
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--launch", type=str, default="", help="tile_rows,zchunk")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
+              "(multi-GPU sharding is a design note only); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2112_09972_amd as sc
+    global wl
+    from paper_2112_09972_amd import workloads as wl
+
+    K, W = args.steps, args.warmup
+    total_steps = (K + W) * STRIDE
+    case = wl.case_c2(nsteps=total_steps + 1)
+    tab = case.tables[0]
+    lat = sc.Lattice(case.n, case.n, case.n, bc="ghost", prec=case.prec, table_len=total_steps, tau=(1.0, 1.0),
+                     g_ab=wl.G_AB, rho_b=case.rho_b, mach_max=wl.MACH_MAX)
+    if args.launch:
+        ty, zc = (int(v) for v in args.launch.split(","))
+        lat.set_launch(ty, zc)
+    lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
+    lat.set_gradient_table(tab[:total_steps], 0)
+    m0, _ = lat.totals()
+    moments = torch.zeros((K + W, 10), dtype=torch.float64, device=lat.device)
+
+    for k in range(W):
+        lat.step(STRIDE)
+        lat.droplet_moments(moments[k])
+    lat.synchronize()
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(lat.stream)
+        lat.step(STRIDE)
+        ev[k][1].record(lat.stream)
+        lat.droplet_moments(moments[W + k])
+    lat.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    step_ms = sum(a.elapsed_time(b) for a, b in ev) / (K * STRIDE)
+    m1, _ = lat.totals()
+    mom = moments.cpu().numpy()
+    axes = np.array([sc.sclbm_droplet_from_moments(mom[i], lat.xc)["semi_axes"] for i in range(K + W)])
+    ca = np.array([wl.capillary(tab[i * STRIDE], case.radius) for i in range(K + W)])
+
+    nodes = case.n ** 3
+    lups = nodes * STRIDE * K
+    mlups = lups / elapsed / 1e6
+    bytes_per_lup = 2 * 19 * 2 * 4  # both components, 19 populations, read + write, FP32
+    achieved = bytes_per_lup * nodes / (step_ms * 1e-3) / 1e9
+    ty, zc = lat.get_launch()
+    out = {
+        "metric": "MLUPS & % HBM peak (2-comp LBM)",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(elapsed * 1e3 / K, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "box": case.n, "radius": case.radius, "lattice_steps_per_step": STRIDE,
+                   "lattice_steps_timed": STRIDE * K, "tau": case.tau, "g_ab": wl.G_AB,
+                   "storage": "fp32 SoA, 2x19 populations", "launch": {"tile_rows": ty, "zchunk": zc},
+                   "ca_max": round(float(ca.max()), 4), "ca_mean": round(float(ca.mean()), 4),
+                   "mass_drift_rel": [float(v) for v in ((m1 - m0) / m0)],
+                   "semi_axes_last": [round(float(v), 4) for v in axes[-1]]},
+        "roofline": {"bound": "hbm", "kernel": "k_step<f32>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(case.name),
+                     "bytes_per_launch": bytes_per_lup * nodes, "avg_launch_ms": round(step_ms, 5)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * sclbm — two-component Shan-Chen lattice Boltzmann droplet solver for MI355X
+ * (gfx950), after Milan, Biferale, Sbragaglia and Toschi, "Sub-Kolmogorov
+ * droplet dynamics in isotropic turbulence using a multiscale Lattice Boltzmann
+ * scheme", arXiv 2112.09972.
+ *
+ * The library time-steps one or more independent cubic boxes (Sec. 3, Fig. 1):
+ * a droplet of component A at the centre of a box of component B, D3Q19
+ * populations for both components, the pair interaction force of Sec. 2 Eq. 7,
+ * single-rate collision (Sec. 2 Eqs. 9-10) and ghost nodes on the faces that hold
+ * the equilibrium (Sec. 2 Eq. 8) of a constant density and the linear velocity
+ * u = A(t) (x - x_c) (Sec. 3 Eq. 14), where A(t) is the velocity-gradient history
+ * that drives the box.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Lattice node (x, y, z), 0 <= x < nx etc.; x_c = ((nx-1)/2, (ny-1)/2, (nz-1)/2)
+ *    is the box centre, the droplet's fixed centre of mass (Sec. 3).
+ *  - Scalar fields are FP64 arrays of nx*ny*nz values, x fastest:
+ *    index = (z*ny + y)*nx + x.  Vector fields are [3][nx*ny*nz].
+ *  - A velocity gradient is 9 doubles, row-major, A[3*i + j] = d u_i / d x_j
+ *    (the paper's G_ij = d_j v_i, Sec. 2 Eq. 2).
+ *  - Time: the state after n steps is "time n".  Step n -> n+1 streams the
+ *    ghost populations built from gradient-table row n.  Observables describe
+ *    the populations after streaming at time n.
+ *  - Pointers named dev_* or documented as device pointers must be device
+ *    memory of the GPU the context runs on; all others are host memory.
+ *  - Every call that launches work enqueues it on the context's stream and
+ *    returns without waiting, except the calls documented to synchronise
+ *    (they return host values).  A context is not thread-safe.
+ *  - Errors: every call returns an sclbm_status; on failure sclbm_last_error()
+ *    returns a thread-local message.  No exception crosses this interface.  A
+ *    call that fails leaves the state as it was unless stated otherwise.
+ *
+ * Ownership: the caller owns the device workspace and every buffer it passes.
+ * The library allocates no device memory; sclbm_destroy frees only the host
+ * context.
+ */
+#ifndef SCLBM_H
+#define SCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SCLBM_OK = 0,
+    SCLBM_EINVAL = -1,    /* bad argument */
+    SCLBM_ESIZE = -2,     /* workspace or buffer too small */
+    SCLBM_EHIP = -3,      /* HIP runtime error */
+    SCLBM_EUNSTABLE = -4, /* NaN/Inf or non-positive density found */
+    SCLBM_ESTATE = -5     /* call not valid in the current state (e.g. stepping past the gradient table) */
+} sclbm_status;
+
+typedef enum {
+    SCLBM_BC_PERIODIC = 0, /* periodic box (test fixture; no ghost nodes) */
+    SCLBM_BC_GHOST = 1     /* ghost nodes with density rho_b and velocity A(t)(x - x_c), Sec. 2 Eq. 8 */
+} sclbm_bc;
+
+typedef enum {
+    SCLBM_F64 = 0,    /* FP64 populations, FP64 arithmetic */
+    SCLBM_F32 = 1,    /* FP32 populations, FP32 arithmetic */
+    SCLBM_F16DEV = 2, /* FP16 deviations f_i - w_i rho_ref, FP32 arithmetic */
+    SCLBM_BF16DEV = 3 /* BF16 deviations f_i - w_i rho_ref, FP32 arithmetic */
+} sclbm_prec;
+
+typedef struct {
+    int32_t nx, ny, nz;  /* nodes per box along x, y, z (each >= 3; nx <= 4096) */
+    int32_t nbox;        /* independent boxes stepped together (>= 1) */
+    int32_t bc;          /* sclbm_bc */
+    int32_t prec;        /* sclbm_prec */
+    int64_t table_len;   /* capacity, in rows, of each box's gradient table (>= 1 in ghost mode) */
+    double tau[2];       /* relaxation times of A and B, each > 1/2 (Sec. 2 Eq. 10) */
+    double g_ab;         /* coupling G_AB = G_BA of Sec. 2 Eq. 7 (G_AA = G_BB = 0) */
+    double rho_b[2];     /* ghost densities of A and B (> 0); in the deviation
+                            precisions also the reference densities rho_ref */
+    double mach_max;     /* if > 0, gradient rows whose ghost speed exceeds
+                            mach_max * c_s (c_s = 1/sqrt 3) are rejected */
+} sclbm_config;
+
+typedef struct {
+    int64_t step;        /* time n of the state measured */
+    double volume;       /* S0: nodes with rho_A > rho_B */
+    double com[3];       /* centre of mass of those nodes */
+    double cov[6];       /* covariance xx, xy, xz, yy, yz, zz about com */
+    double semi_axes[3]; /* a_k = sqrt(5 lambda_k), descending (uniform-ellipsoid relation) */
+    double deformation;  /* D = (a_1 - a_3)/(a_1 + a_3), Sec. 2 Eq. 4 */
+    double r_eq;         /* (3 S0 / 4 pi)^(1/3) */
+} sclbm_droplet_stats;
+
+typedef struct sclbm_ctx sclbm_ctx;
+
+/* Bytes of device workspace a context with this configuration needs.
+ * Errors: EINVAL for an invalid configuration. */
+sclbm_status sclbm_workspace_bytes(const sclbm_config *cfg, size_t *bytes);
+
+/* Create a context on the current HIP device.  dev_workspace: device memory of
+ * at least sclbm_workspace_bytes bytes, 256-byte aligned, owned by the caller and
+ * kept alive until sclbm_destroy.  hip_stream: the hipStream_t every call
+ * enqueues on (NULL = the null stream).  The populations are undefined until an
+ * init call.  Errors: EINVAL (config), ESIZE (workspace too small or misaligned). */
+sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
+                          sclbm_ctx **out);
+
+/* Free the host context.  Does not touch device memory. */
+sclbm_status sclbm_destroy(sclbm_ctx *ctx);
+
+/* Initial state of one box (box = -1: every box): a spherical droplet of A of
+ * radius `radius` centred at center[3], density
+ *   rho_A = (rho_in + rho_out)/2 - (rho_in - rho_out)/2 tanh((r - radius)/width),
+ *   rho_B = rho_in + rho_out - rho_A,
+ * velocity u = A0 (x - x_c) (A0 may be NULL for rest), and populations at
+ * equilibrium g_eq(rho_sigma, u) (Sec. 2 Eq. 8).  Resets the time to 0.
+ * The paper places the droplet at the box centre (Sec. 3, Fig. 1) and gives no
+ * profile; the tanh profile is this library's choice. */
+sclbm_status sclbm_init_droplet(sclbm_ctx *ctx, int32_t box, const double center[3], double radius,
+                                double width, double rho_in, double rho_out, const double A0[9]);
+
+/* Initial state of one box from FP64 device fields rho_a[N], rho_b[N], u[3][N]
+ * (u may be NULL for rest): populations at equilibrium.  Resets the time to 0. */
+sclbm_status sclbm_init_fields(sclbm_ctx *ctx, int32_t box, const double *rho_a, const double *rho_b,
+                               const double *u);
+
+/* Copy n rows of a box's velocity-gradient table from host memory: row t drives
+ * step first_step + t (Sec. 3 Eq. 14; Sec. 4 holds each sample of the turbulent
+ * gradient for a number of steps, the caller expands it into per-step rows).
+ * n <= table_len.  With mach_max > 0 every row is checked on every ghost node
+ * (|A (x_g - x_c)| <= mach_max c_s) and the call fails with EINVAL naming the
+ * first offending row; the previous table then stays in force. */
+sclbm_status sclbm_set_gradient_table(sclbm_ctx *ctx, int32_t box, const double *A_rows, int64_t first_step,
+                                      int64_t n);
+
+/* Advance every box by nsteps (fused stream-collide update, one kernel launch
+ * per step).  In ghost mode every box's table must cover steps n..n+nsteps-1,
+ * else ESTATE and nothing is launched. */
+sclbm_status sclbm_step(sclbm_ctx *ctx, int64_t nsteps);
+
+/* Current time n. */
+sclbm_status sclbm_get_step(const sclbm_ctx *ctx, int64_t *step);
+
+/* Observables of one box at time n into FP64 device arrays: densities rho_a[N],
+ * rho_b[N] (Sec. 2 Eq. 6, per component) and, if u != NULL, the barycentric
+ * velocity u[3][N] = (j_A + j_B + (F_A + F_B)/2)/(rho_A + rho_B) (Sec. 2 Eq. 6
+ * with the half-force term of the Shan-Chen model; F from Sec. 2 Eq. 7).
+ * rho_a and rho_b must not be NULL. */
+sclbm_status sclbm_fields(sclbm_ctx *ctx, int32_t box, double *rho_a, double *rho_b, double *u);
+
+/* FP64 totals of one box at time n: mass[2] = sum rho_A, sum rho_B and
+ * momentum[3] = sum (j_A + j_B).  Deterministic fixed-order reduction.
+ * Synchronises the stream.  EUNSTABLE if a NaN/Inf or non-positive density is
+ * found (the totals are still returned). */
+sclbm_status sclbm_totals(sclbm_ctx *ctx, int32_t box, double mass[2], double momentum[3]);
+
+/* Indicator moments of one box at time n, phi = [rho_A > rho_B], about x_c,
+ * written as 10 FP64 values to device memory: S0, S1x, S1y, S1z, S2xx, S2xy,
+ * S2xz, S2yy, S2yz, S2zz.  Does not synchronise (for time series: collect many,
+ * copy once). */
+sclbm_status sclbm_droplet_moments(sclbm_ctx *ctx, int32_t box, double *dev_out10);
+
+/* Droplet statistics from 10 indicator moments about `center` (host only, no
+ * GPU work): covariance, its eigenvalues by the closed-form trigonometric
+ * method for symmetric 3x3 matrices, semi-axes, deformation (Sec. 2 Eq. 4). */
+sclbm_status sclbm_droplet_from_moments(const double moments[10], const double center[3], int64_t step,
+                                        sclbm_droplet_stats *out);
+
+/* sclbm_droplet_moments + copy + sclbm_droplet_from_moments.  Synchronises. */
+sclbm_status sclbm_droplet(sclbm_ctx *ctx, int32_t box, sclbm_droplet_stats *out);
+
+/* Global velocity error E0 of Sec. 4 Eq. 16 for one box at time n against the
+ * linear flow A (x - x_c): sqrt(<|u - A(x - x_c)|^2>) / sqrt(<|A(x - x_c)|^2>),
+ * averages over the box's nodes, u as in sclbm_fields.  Synchronises. */
+sclbm_status sclbm_velocity_error(sclbm_ctx *ctx, int32_t box, const double A[9], double *e0);
+
+/* Checkpoint: bytes needed, save the state (populations of every box, time)
+ * into host memory, restore it.  Save synchronises; load is bitwise exact. */
+sclbm_status sclbm_state_bytes(const sclbm_ctx *ctx, size_t *bytes);
+sclbm_status sclbm_save(sclbm_ctx *ctx, void *host_buf, size_t bytes);
+sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
+
+/* Launch shape of the step kernel: rows per tile (2, 4 or 8) and planes per
+ * z-chunk (>= 1).  Both only change speed, never results. */
+sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk);
+sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *sclbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCLBM_H */

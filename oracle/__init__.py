@@ -71,6 +71,7 @@ def _load():
         lib.orc_droplet_moments.argtypes = [I, I, I, dp, dp, dp, dp]
         lib.orc_stencil.argtypes = [ip, dp]
         lib.orc_equilibrium.argtypes = [D, dp, dp]
+        lib.orc_num_threads.restype = I
         _lib = lib
     return _lib
 
@@ -87,6 +88,11 @@ def stencil():
     w = np.zeros(Q, dtype=np.float64)
     lib.orc_stencil(c.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _dp(w))
     return c.astype(np.int64), w
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(_load().orc_num_threads())
 
 
 def equilibrium(rho: float, u) -> np.ndarray:

@@ -38,6 +38,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
 
@@ -106,6 +109,15 @@ static double geq(int i, double rho, const double u[3]) {
 }
 
 int orc_q(void) { return Q; }
+
+/* Threads the OpenMP loops of this oracle use. */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 void orc_stencil(int *c_out /* [Q][3] */, double *w_out /* [Q] */) {
     orc_stencil_init();

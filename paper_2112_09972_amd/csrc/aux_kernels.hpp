@@ -1,0 +1,257 @@
+// Initialisation, observables and FP64 reductions (arXiv 2112.09972, Sec. 2
+// Eqs. 6-8, Sec. 4 Eq. 16; droplet inertia tensor for Sec. 2 Eq. 4).
+//
+// Reductions are deterministic: a fixed grid of NRED_BLOCKS workgroups, each
+// thread accumulating a fixed strided subset of nodes in FP64, a wavefront
+// butterfly (64 lanes), a fixed-order pass over the wavefronts in LDS, one
+// partial per workgroup, then one workgroup summing the partials in a fixed
+// order.  No atomics anywhere, so repeated runs give identical bits.
+#pragma once
+
+#include "lattice.hpp"
+
+namespace sclbm {
+
+constexpr int NRED_BLOCKS = 512;
+constexpr int NRED_THREADS = 256;
+constexpr int NSTAT = 16;  // mass 2, momentum 3, S0, S1 3, S2 6, bad-node count
+
+struct Mat3 {
+    double a[9];  // row-major, a[3*i + j] = d u_i / d x_j
+};
+
+struct BoxGeom {
+    int nx, ny, nz;
+    int64_t nnode;
+    double xc[3];
+};
+
+__device__ __forceinline__ void node_xyz(const BoxGeom &g, int64_t k, int &x, int &y, int &z) {
+    x = (int)(k % g.nx);
+    int64_t t = k / g.nx;
+    y = (int)(t % g.ny);
+    z = (int)(t / g.ny);
+}
+
+struct DropletInit {
+    double ctr[3], radius, width, rho_in, rho_out;
+    Mat3 A0;
+};
+
+// mode 0: tanh droplet (DropletInit); mode 1: FP64 fields rho_a, rho_b, u.
+template <int P>
+__global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, BoxGeom g, int mode, DropletInit d,
+                                              const double *rho_a, const double *rho_b, const double *u,
+                                              double rref0, double rref1) {
+    using R = typename Prec<P>::R;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.nnode) return;
+    int x, y, z;
+    node_xyz(g, k, x, y, z);
+    double ra, rb, ux, uy, uz;
+    if (mode == 0) {
+        // tanh droplet, linear velocity about the box centre
+        const double dx = x - d.ctr[0], dy = y - d.ctr[1], dz = z - d.ctr[2];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        ra = 0.5 * (d.rho_in + d.rho_out) - 0.5 * (d.rho_in - d.rho_out) * tanh((r - d.radius) / d.width);
+        rb = d.rho_in + d.rho_out - ra;
+        const double ex = x - g.xc[0], ey = y - g.xc[1], ez = z - g.xc[2];
+        const double *A = d.A0.a;
+        ux = A[0] * ex + A[1] * ey + A[2] * ez;
+        uy = A[3] * ex + A[4] * ey + A[5] * ez;
+        uz = A[6] * ex + A[7] * ey + A[8] * ez;
+    } else {
+        ra = rho_a[k];
+        rb = rho_b[k];
+        if (u) {
+            ux = u[k];
+            uy = u[g.nnode + k];
+            uz = u[2 * g.nnode + k];
+        } else {
+            ux = uy = uz = 0.0;
+        }
+    }
+    const double usq = ux * ux + uy * uy + uz * uz;
+    const double rr[2] = {ra, rb};
+    const double rref[2] = {rref0, rref1};
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double fe = equilibrium<double>(i, rr[s], ux, uy, uz, usq);
+            Prec<P>::store(f + (int64_t)(s * Q + i) * g.nnode + k, R(fe), R(w_of<double>(i) * rref[s]));
+        }
+}
+
+template <int P>
+__device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, int64_t N, int64_t k, const double rref[2],
+                                             double rho[2], double j[2][3]) {
+    using R = typename Prec<P>::R;
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        R r = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const R v = R(Prec<P>::load(f + (int64_t)(s * Q + i) * N + k, R(w_of<double>(i) * rref[s])));
+            r += v;
+            if (cx_of(i)) jx += R(cx_of(i)) * v;
+            if (cy_of(i)) jy += R(cy_of(i)) * v;
+            if (cz_of(i)) jz += R(cz_of(i)) * v;
+        }
+        rho[s] = double(r);
+        j[s][0] = double(jx);
+        j[s][1] = double(jy);
+        j[s][2] = double(jz);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_density(const typename Prec<P>::S *f, BoxGeom g, double rref0, double rref1,
+                                                 double *rho_a, double *rho_b) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.nnode) return;
+    const double rref[2] = {rref0, rref1};
+    double rho[2], j[2][3];
+    node_moments<P>(f, g.nnode, k, rref, rho, j);
+    rho_a[k] = rho[0];
+    rho_b[k] = rho[1];
+}
+
+// Barycentric velocity with the half-force term; force from the FP64 density
+// arrays written by k_density (same neighbour rules as the step kernel).
+template <int P>
+__global__ __launch_bounds__(256) void k_velocity(const typename Prec<P>::S *f, BoxGeom g, double rref0, double rref1,
+                                                  const double *rho_a, const double *rho_b, int ghost, double gab,
+                                                  double rb0, double rb1, double *u) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= g.nnode) return;
+    const double rref[2] = {rref0, rref1};
+    double rho[2], j[2][3];
+    node_moments<P>(f, g.nnode, k, rref, rho, j);
+    int x, y, z;
+    node_xyz(g, k, x, y, z);
+    const double *rf[2] = {rho_a, rho_b};
+    const double rbnd[2] = {rb0, rb1};
+    double Ft[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int o = 1 - s;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            int nxp = x + cx_of(i), nyp = y + cy_of(i), nzp = z + cz_of(i);
+            double nb;
+            const bool inside = nxp >= 0 && nxp < g.nx && nyp >= 0 && nyp < g.ny && nzp >= 0 && nzp < g.nz;
+            if (inside || !ghost) {
+                nxp = (nxp + g.nx) % g.nx;
+                nyp = (nyp + g.ny) % g.ny;
+                nzp = (nzp + g.nz) % g.nz;
+                nb = rf[o][((int64_t)nzp * g.ny + nyp) * g.nx + nxp];
+            } else {
+                nb = rbnd[o];
+            }
+            const double wn = w_of<double>(i) * nb;
+            sx += cx_of(i) * wn;
+            sy += cy_of(i) * wn;
+            sz += cz_of(i) * wn;
+        }
+        const double pre = -gab * rho[s];
+        Ft[0] += pre * sx;
+        Ft[1] += pre * sy;
+        Ft[2] += pre * sz;
+    }
+    const double rt = rho[0] + rho[1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c * g.nnode + k] = (j[0][c] + j[1][c] + 0.5 * Ft[c]) / rt;
+}
+
+template <int K>
+__device__ __forceinline__ void block_reduce_store(double (&v)[K], double *out /* K values */) {
+    // wavefront butterfly, fixed order
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_down(v[c], off, 64);
+    }
+    __shared__ double part[NRED_THREADS / 64][K];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < K; ++c) part[wv][c] = v[c];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double acc = 0.0;
+        for (int w = 0; w < NRED_THREADS / 64; ++w) acc += part[w][threadIdx.x];
+        out[threadIdx.x] = acc;
+    }
+}
+
+// Per-workgroup partials of: mass A, mass B, momentum (3), indicator moments
+// S0, S1 (3), S2 (6) about the box centre, and the count of bad nodes.
+template <int P>
+__global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::S *f, BoxGeom g, double rref0,
+                                                        double rref1, double *partial) {
+    double v[NSTAT];
+#pragma unroll
+    for (int c = 0; c < NSTAT; ++c) v[c] = 0.0;
+    const double rref[2] = {rref0, rref1};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.nnode; k += stride) {
+        double rho[2], j[2][3];
+        node_moments<P>(f, g.nnode, k, rref, rho, j);
+        v[0] += rho[0];
+        v[1] += rho[1];
+        v[2] += j[0][0] + j[1][0];
+        v[3] += j[0][1] + j[1][1];
+        v[4] += j[0][2] + j[1][2];
+        if (!(rho[0] > 0.0) || !(rho[1] > 0.0) || !isfinite(rho[0]) || !isfinite(rho[1])) v[15] += 1.0;
+        if (rho[0] > rho[1]) {
+            int x, y, z;
+            node_xyz(g, k, x, y, z);
+            const double dx = x - g.xc[0], dy = y - g.xc[1], dz = z - g.xc[2];
+            v[5] += 1.0;
+            v[6] += dx;
+            v[7] += dy;
+            v[8] += dz;
+            v[9] += dx * dx;
+            v[10] += dx * dy;
+            v[11] += dx * dz;
+            v[12] += dy * dy;
+            v[13] += dy * dz;
+            v[14] += dz * dz;
+        }
+    }
+    block_reduce_store<NSTAT>(v, partial + (int64_t)blockIdx.x * NSTAT);
+}
+
+// Partials of sum |u - A d|^2 and sum |A d|^2 (Sec. 4 Eq. 16).
+__global__ __launch_bounds__(NRED_THREADS) void k_e0(const double *u, BoxGeom g, Mat3 A, double *partial) {
+    double v[2] = {0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.nnode; k += stride) {
+        int x, y, z;
+        node_xyz(g, k, x, y, z);
+        const double dx = x - g.xc[0], dy = y - g.xc[1], dz = z - g.xc[2];
+        const double vx = A.a[0] * dx + A.a[1] * dy + A.a[2] * dz;
+        const double vy = A.a[3] * dx + A.a[4] * dy + A.a[5] * dz;
+        const double vz = A.a[6] * dx + A.a[7] * dy + A.a[8] * dz;
+        const double ex = u[k] - vx, ey = u[g.nnode + k] - vy, ez = u[2 * g.nnode + k] - vz;
+        v[0] += ex * ex + ey * ey + ez * ez;
+        v[1] += vx * vx + vy * vy + vz * vz;
+    }
+    block_reduce_store<2>(v, partial + (int64_t)blockIdx.x * 2);
+}
+
+// Fixed-order sum of nblk partials of K values each.
+template <int K>
+__global__ __launch_bounds__(NRED_THREADS) void k_final(const double *partial, int nblk, double *out) {
+    double v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += NRED_THREADS)
+#pragma unroll
+        for (int c = 0; c < K; ++c) v[c] += partial[(int64_t)b * K + c];
+    block_reduce_store<K>(v, out);
+}
+
+}  // namespace sclbm

@@ -1,0 +1,641 @@
+// C-ABI host library of the two-component Shan-Chen lattice Boltzmann solver
+// (arXiv 2112.09972).  Declarations and the contract of every call: sclbm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "aux_kernels.hpp"
+#include "lattice.hpp"
+#include "sclbm.h"
+#include "step_kernel.hpp"
+
+using namespace sclbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+sclbm_status fail(sclbm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(SCLBM_EHIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                          \
+    } while (0)
+
+#define HIP_LAUNCHED()                                                                                  \
+    do {                                                                                                \
+        hipError_t e_ = hipGetLastError();                                                              \
+        if (e_ != hipSuccess) return fail(SCLBM_EHIP, "kernel launch: %s (%s:%d)", hipGetErrorString(e_), \
+                                          __FILE__, __LINE__);                                          \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t f0, f1, atab, first, clock, partial, result, diag, total;
+    size_t fbytes;
+};
+
+bool config_ok(const sclbm_config *c, std::string &why) {
+    if (!c) { why = "null config"; return false; }
+    if (c->nx < 3 || c->ny < 3 || c->nz < 3) { why = "nx, ny, nz must be >= 3"; return false; }
+    if (c->nx > 4096 || c->ny > 65535 || c->nz > 65535) { why = "box too large"; return false; }
+    if (c->nbox < 1) { why = "nbox must be >= 1"; return false; }
+    if (c->bc != SCLBM_BC_PERIODIC && c->bc != SCLBM_BC_GHOST) { why = "unknown boundary mode"; return false; }
+    if (c->prec < SCLBM_F64 || c->prec > SCLBM_BF16DEV) { why = "unknown precision"; return false; }
+    if (!(c->tau[0] > 0.5) || !(c->tau[1] > 0.5)) { why = "tau must exceed 1/2"; return false; }
+    if (!(c->rho_b[0] > 0.0) || !(c->rho_b[1] > 0.0)) { why = "rho_b must be positive"; return false; }
+    if (!std::isfinite(c->g_ab)) { why = "g_ab must be finite"; return false; }
+    if (!(c->mach_max >= 0.0)) { why = "mach_max must be >= 0"; return false; }
+    if (c->bc == SCLBM_BC_GHOST && c->table_len < 1) { why = "ghost mode needs table_len >= 1"; return false; }
+    if (c->table_len < 0) { why = "table_len must be >= 0"; return false; }
+    const double nodes = double(c->nx) * c->ny * c->nz * c->nbox;
+    if (nodes * 2 * Q * elem_bytes(c->prec) > 250e9) { why = "populations exceed 250 GB"; return false; }
+    return true;
+}
+
+Layout make_layout(const sclbm_config *c) {
+    Layout L{};
+    const size_t N = size_t(c->nx) * c->ny * c->nz;
+    L.fbytes = size_t(c->nbox) * 2 * Q * N * elem_bytes(c->prec);
+    size_t off = 0;
+    L.f0 = off; off += round_up(L.fbytes);
+    L.f1 = off; off += round_up(L.fbytes);
+    L.atab = off; off += round_up(size_t(c->nbox) * size_t(c->bc == SCLBM_BC_GHOST ? c->table_len : 0) * 9 * 8);
+    L.first = off; off += round_up(size_t(c->nbox) * 8);
+    L.clock = off; off += round_up(2 * 8);
+    L.partial = off; off += round_up(size_t(NRED_BLOCKS) * NSTAT * 8);
+    L.result = off; off += round_up(NSTAT * 8);
+    L.diag = off; off += round_up(5 * N * 8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct sclbm_ctx {
+    sclbm_config cfg;
+    Layout lay;
+    char *ws;
+    hipStream_t stream;
+    int64_t n;        // time of the state
+    int par;          // which population buffer holds f(n): 0 -> f0
+    int tile_rows;    // TY
+    int zchunk;
+    std::vector<int64_t> tab_first, tab_len;  // host copies, per box
+    int64_t N;
+    BoxGeom geom;
+
+    void *fbuf(int which) { return ws + (which ? lay.f1 : lay.f0); }
+    size_t box_bytes() const { return size_t(2) * Q * size_t(N) * elem_bytes(cfg.prec); }
+    double *partial() { return reinterpret_cast<double *>(ws + lay.partial); }
+    double *result() { return reinterpret_cast<double *>(ws + lay.result); }
+    double *diag() { return reinterpret_cast<double *>(ws + lay.diag); }
+    int64_t *clock() { return reinterpret_cast<int64_t *>(ws + lay.clock); }
+};
+
+namespace {
+
+sclbm_status check_ctx(const sclbm_ctx *c) {
+    if (!c) return fail(SCLBM_EINVAL, "null context");
+    return SCLBM_OK;
+}
+
+sclbm_status check_box(const sclbm_ctx *c, int32_t box, bool allow_all) {
+    if (allow_all && box == -1) return SCLBM_OK;
+    if (box < 0 || box >= c->cfg.nbox) return fail(SCLBM_EINVAL, "box %d out of range [0, %d)", box, c->cfg.nbox);
+    return SCLBM_OK;
+}
+
+int default_zchunk(const sclbm_config &c, int ty) {
+    const long tiles = long((c.nx + 63) / 64) * long((c.ny + ty - 1) / ty) * c.nbox;
+    long zc = (tiles * c.nz) / 1024;  // aim at >= 1024 workgroups (4 per CU)
+    zc = std::max(2L, std::min(zc, long(c.nz)));
+    return int(zc);
+}
+
+// Launch of the step kernel for precision P and tile rows TY.
+template <int P, int TY>
+hipError_t launch_step_ty(sclbm_ctx *c, const StepArgs &a) {
+    dim3 block(64, TY, 1);
+    dim3 grid((c->cfg.nx + 63) / 64, (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
+    hipLaunchKernelGGL((k_step<P, TY>), grid, block, 0, c->stream, a);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_step(sclbm_ctx *c, const StepArgs &a) {
+    switch (c->tile_rows) {
+        case 2: return launch_step_ty<P, 2>(c, a);
+        case 8: return launch_step_ty<P, 8>(c, a);
+        default: return launch_step_ty<P, 4>(c, a);
+    }
+}
+
+hipError_t launch_step_prec(sclbm_ctx *c, const StepArgs &a) {
+    switch (c->cfg.prec) {
+        case SCLBM_F64: return launch_step<SCLBM_F64>(c, a);
+        case SCLBM_F32: return launch_step<SCLBM_F32>(c, a);
+        case SCLBM_F16DEV: return launch_step<SCLBM_F16DEV>(c, a);
+        default: return launch_step<SCLBM_BF16DEV>(c, a);
+    }
+}
+
+// Dispatch a per-precision functor.
+template <typename Fn>
+hipError_t by_prec(int prec, Fn &&fn) {
+    switch (prec) {
+        case SCLBM_F64: return fn(std::integral_constant<int, SCLBM_F64>{});
+        case SCLBM_F32: return fn(std::integral_constant<int, SCLBM_F32>{});
+        case SCLBM_F16DEV: return fn(std::integral_constant<int, SCLBM_F16DEV>{});
+        default: return fn(std::integral_constant<int, SCLBM_BF16DEV>{});
+    }
+}
+
+unsigned grid1d(int64_t n, int bs) { return unsigned((n + bs - 1) / bs); }
+
+sclbm_status init_common(sclbm_ctx *c, int32_t box, int mode, const DropletInit &d, const double *ra, const double *rb,
+                         const double *u) {
+    const int b0 = box < 0 ? 0 : box, b1 = box < 0 ? c->cfg.nbox : box + 1;
+    // written into the buffer that holds the current state of every box
+    for (int b = b0; b < b1; ++b) {
+        hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
+            constexpr int P = decltype(pc)::value;
+            using S = typename Prec<P>::S;
+            S *f = reinterpret_cast<S *>(c->fbuf(c->par)) + size_t(b) * 2 * Q * size_t(c->N);
+            hipLaunchKernelGGL((k_init<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f, c->geom, mode, d, ra,
+                               rb, u, c->cfg.rho_b[0], c->cfg.rho_b[1]);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return fail(SCLBM_EHIP, "init kernel: %s", hipGetErrorString(e));
+    }
+    c->n = 0;
+    int64_t zero[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(c->clock(), zero, sizeof zero, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));  // `zero` is a stack buffer
+    return SCLBM_OK;
+}
+
+// Largest ghost speed |A (x_g - x_c)| of a gradient over the ghost nodes that
+// streaming reads.  |A d| is convex in d, so the maximum over the face and edge
+// ghosts is reached at an end point of an edge ghost line: two coordinates in
+// {-1, n} and the third in {0, n-1}.
+double max_ghost_speed(const sclbm_config &c, const double *A, const double xc[3]) {
+    const int n[3] = {c.nx, c.ny, c.nz};
+    double best = 0.0;
+    for (int free_axis = 0; free_axis < 3; ++free_axis)
+        for (int m = 0; m < 8; ++m) {
+            double p[3];
+            for (int ax = 0, bit = 0; ax < 3; ++ax, ++bit) {
+                const int hi = (m >> bit) & 1;
+                if (ax == free_axis)
+                    p[ax] = hi ? n[ax] - 1 : 0;
+                else
+                    p[ax] = hi ? n[ax] : -1;
+            }
+            const double d[3] = {p[0] - xc[0], p[1] - xc[1], p[2] - xc[2]};
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i) {
+                const double v = A[3 * i] * d[0] + A[3 * i + 1] * d[1] + A[3 * i + 2] * d[2];
+                s += v * v;
+            }
+            best = std::max(best, std::sqrt(s));
+        }
+    return best;
+}
+
+// Eigenvalues of a symmetric 3x3 matrix, descending, by the closed-form
+// trigonometric solution of the characteristic cubic.
+void sym3_eigenvalues(const double m[6] /* xx xy xz yy yz zz */, double out[3]) {
+    const double a00 = m[0], a01 = m[1], a02 = m[2], a11 = m[3], a12 = m[4], a22 = m[5];
+    const double p1 = a01 * a01 + a02 * a02 + a12 * a12;
+    const double q = (a00 + a11 + a22) / 3.0;
+    const double b00 = a00 - q, b11 = a11 - q, b22 = a22 - q;
+    const double p2 = b00 * b00 + b11 * b11 + b22 * b22 + 2.0 * p1;
+    if (p2 <= 0.0) {
+        out[0] = out[1] = out[2] = q;
+        return;
+    }
+    const double p = std::sqrt(p2 / 6.0);
+    // det((A - qI)/p) / 2
+    const double c00 = b00 / p, c11 = b11 / p, c22 = b22 / p, c01 = a01 / p, c02 = a02 / p, c12 = a12 / p;
+    const double det = c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02);
+    double r = det / 2.0;
+    r = std::max(-1.0, std::min(1.0, r));
+    const double phi = std::acos(r) / 3.0;
+    const double two_pi_3 = 2.0943951023931954923;
+    out[0] = q + 2.0 * p * std::cos(phi);
+    out[2] = q + 2.0 * p * std::cos(phi + two_pi_3);
+    out[1] = 3.0 * q - out[0] - out[2];
+}
+
+template <int K>
+sclbm_status reduce_final(sclbm_ctx *c, int nblk, double *host_out) {
+    hipLaunchKernelGGL((k_final<K>), dim3(1), dim3(NRED_THREADS), 0, c->stream, c->partial(), nblk, c->result());
+    HIP_LAUNCHED();
+    HIP_TRY(hipMemcpyAsync(host_out, c->result(), K * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCLBM_OK;
+}
+
+// Launch the FP64 partial statistics of one box at time n; final values go to
+// c->result() (device) after k_final.
+sclbm_status launch_stats(sclbm_ctx *c, int32_t box) {
+    hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        using S = typename Prec<P>::S;
+        const S *f = reinterpret_cast<const S *>(c->fbuf(c->par)) + size_t(box) * 2 * Q * size_t(c->N);
+        hipLaunchKernelGGL((k_stats<P>), dim3(NRED_BLOCKS), dim3(NRED_THREADS), 0, c->stream, f, c->geom,
+                           c->cfg.rho_b[0], c->cfg.rho_b[1], c->partial());
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return fail(SCLBM_EHIP, "stats kernel: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL((k_final<NSTAT>), dim3(1), dim3(NRED_THREADS), 0, c->stream, c->partial(), NRED_BLOCKS,
+                       c->result());
+    HIP_LAUNCHED();
+    return SCLBM_OK;
+}
+
+sclbm_status fields_into(sclbm_ctx *c, int32_t box, double *ra, double *rb, double *u) {
+    hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        using S = typename Prec<P>::S;
+        const S *f = reinterpret_cast<const S *>(c->fbuf(c->par)) + size_t(box) * 2 * Q * size_t(c->N);
+        hipLaunchKernelGGL((k_density<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f, c->geom,
+                           c->cfg.rho_b[0], c->cfg.rho_b[1], ra, rb);
+        hipError_t e1 = hipGetLastError();
+        if (e1 != hipSuccess || !u) return e1;
+        hipLaunchKernelGGL((k_velocity<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f, c->geom,
+                           c->cfg.rho_b[0], c->cfg.rho_b[1], ra, rb, int(c->cfg.bc == SCLBM_BC_GHOST), c->cfg.g_ab,
+                           c->cfg.rho_b[0], c->cfg.rho_b[1], u);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return fail(SCLBM_EHIP, "fields kernels: %s", hipGetErrorString(e));
+    return SCLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sclbm_last_error(void) { return g_err.c_str(); }
+
+sclbm_status sclbm_workspace_bytes(const sclbm_config *cfg, size_t *bytes) {
+    std::string why;
+    if (!bytes) return fail(SCLBM_EINVAL, "null bytes pointer");
+    if (!config_ok(cfg, why)) return fail(SCLBM_EINVAL, "invalid config: %s", why.c_str());
+    *bytes = make_layout(cfg).total;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
+                          sclbm_ctx **out) {
+    std::string why;
+    if (!out) return fail(SCLBM_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!config_ok(cfg, why)) return fail(SCLBM_EINVAL, "invalid config: %s", why.c_str());
+    const Layout lay = make_layout(cfg);
+    if (!dev_workspace) return fail(SCLBM_EINVAL, "null workspace");
+    if (bytes < lay.total) return fail(SCLBM_ESIZE, "workspace %zu bytes < required %zu", bytes, lay.total);
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) return fail(SCLBM_ESIZE, "workspace not 256-byte aligned");
+    sclbm_ctx *c = new (std::nothrow) sclbm_ctx();
+    if (!c) return fail(SCLBM_EINVAL, "host allocation failed");
+    c->cfg = *cfg;
+    c->lay = lay;
+    c->ws = static_cast<char *>(dev_workspace);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->n = 0;
+    c->par = 0;
+    c->tile_rows = 4;
+    c->zchunk = default_zchunk(*cfg, 4);
+    c->tab_first.assign(cfg->nbox, 0);
+    c->tab_len.assign(cfg->nbox, 0);
+    c->N = int64_t(cfg->nx) * cfg->ny * cfg->nz;
+    c->geom.nx = cfg->nx;
+    c->geom.ny = cfg->ny;
+    c->geom.nz = cfg->nz;
+    c->geom.nnode = c->N;
+    c->geom.xc[0] = 0.5 * (cfg->nx - 1);
+    c->geom.xc[1] = 0.5 * (cfg->ny - 1);
+    c->geom.xc[2] = 0.5 * (cfg->nz - 1);
+    std::vector<int64_t> zeros(std::max(2, cfg->nbox), 0);
+    hipError_t e = hipMemcpyAsync(c->ws + lay.first, zeros.data(), size_t(cfg->nbox) * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->clock(), zeros.data(), 16, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(SCLBM_EHIP, "create: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_destroy(sclbm_ctx *ctx) {
+    delete ctx;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_init_droplet(sclbm_ctx *c, int32_t box, const double center[3], double radius, double width,
+                                double rho_in, double rho_out, const double A0[9]) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, true))) return st;
+    if (!center) return fail(SCLBM_EINVAL, "null center");
+    if (!(width > 0.0) || !(radius >= 0.0)) return fail(SCLBM_EINVAL, "need width > 0 and radius >= 0");
+    if (!(rho_in > 0.0) || !(rho_out > 0.0)) return fail(SCLBM_EINVAL, "densities must be positive");
+    DropletInit d{};
+    for (int k = 0; k < 3; ++k) d.ctr[k] = center[k];
+    d.radius = radius;
+    d.width = width;
+    d.rho_in = rho_in;
+    d.rho_out = rho_out;
+    for (int k = 0; k < 9; ++k) d.A0.a[k] = A0 ? A0[k] : 0.0;
+    return init_common(c, box, 0, d, nullptr, nullptr, nullptr);
+}
+
+sclbm_status sclbm_init_fields(sclbm_ctx *c, int32_t box, const double *rho_a, const double *rho_b, const double *u) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, false))) return st;
+    if (!rho_a || !rho_b) return fail(SCLBM_EINVAL, "null density field");
+    DropletInit d{};
+    return init_common(c, box, 1, d, rho_a, rho_b, u);
+}
+
+sclbm_status sclbm_set_gradient_table(sclbm_ctx *c, int32_t box, const double *A, int64_t first_step, int64_t n) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, false))) return st;
+    if (c->cfg.bc != SCLBM_BC_GHOST) return fail(SCLBM_ESTATE, "gradient table needs the ghost boundary");
+    if (!A) return fail(SCLBM_EINVAL, "null table");
+    if (n < 1 || n > c->cfg.table_len) return fail(SCLBM_EINVAL, "n=%lld outside [1, table_len=%lld]", (long long)n,
+                                                   (long long)c->cfg.table_len);
+    if (first_step < 0) return fail(SCLBM_EINVAL, "first_step must be >= 0");
+    for (int64_t t = 0; t < n; ++t)
+        for (int k = 0; k < 9; ++k)
+            if (!std::isfinite(A[9 * t + k])) return fail(SCLBM_EINVAL, "row %lld has a non-finite entry", (long long)t);
+    if (c->cfg.mach_max > 0.0) {
+        const double vmax = c->cfg.mach_max / std::sqrt(3.0);
+        for (int64_t t = 0; t < n; ++t) {
+            const double v = max_ghost_speed(c->cfg, A + 9 * t, c->geom.xc);
+            if (v > vmax)
+                return fail(SCLBM_EINVAL, "row %lld: ghost speed %.6g exceeds mach_max*c_s = %.6g", (long long)t, v, vmax);
+        }
+    }
+    double *dtab = reinterpret_cast<double *>(c->ws + c->lay.atab) + size_t(box) * size_t(c->cfg.table_len) * 9;
+    HIP_TRY(hipMemcpyAsync(dtab, A, size_t(n) * 9 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    int64_t *dfirst = reinterpret_cast<int64_t *>(c->ws + c->lay.first) + box;
+    HIP_TRY(hipMemcpyAsync(dfirst, &first_step, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));  // host sources may be released on return
+    c->tab_first[box] = first_step;
+    c->tab_len[box] = n;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_step(sclbm_ctx *c, int64_t nsteps) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (nsteps < 0) return fail(SCLBM_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return SCLBM_OK;
+    const bool ghost = c->cfg.bc == SCLBM_BC_GHOST;
+    if (ghost)
+        for (int b = 0; b < c->cfg.nbox; ++b)
+            if (c->n < c->tab_first[b] || c->n + nsteps > c->tab_first[b] + c->tab_len[b])
+                return fail(SCLBM_ESTATE, "box %d: gradient table covers steps [%lld, %lld), need [%lld, %lld)", b,
+                            (long long)c->tab_first[b], (long long)(c->tab_first[b] + c->tab_len[b]),
+                            (long long)c->n, (long long)(c->n + nsteps));
+    StepArgs a{};
+    a.atab = reinterpret_cast<const double *>(c->ws + c->lay.atab);
+    a.tab_first = reinterpret_cast<const int64_t *>(c->ws + c->lay.first);
+    a.table_len = c->cfg.table_len;
+    a.nnode = c->N;
+    a.nx = c->cfg.nx;
+    a.ny = c->cfg.ny;
+    a.nz = c->cfg.nz;
+    a.zchunk = c->zchunk;
+    a.nzc = (c->cfg.nz + c->zchunk - 1) / c->zchunk;
+    a.ghost = ghost ? 1 : 0;
+    for (int s = 0; s < 2; ++s) {
+        a.tau[s] = c->cfg.tau[s];
+        a.omega[s] = 1.0 / c->cfg.tau[s];
+        a.rho_b[s] = c->cfg.rho_b[s];
+        a.rho_ref[s] = c->cfg.rho_b[s];
+    }
+    a.g = c->cfg.g_ab;
+    for (int k = 0; k < 3; ++k) a.xc[k] = c->geom.xc[k];
+    for (int64_t t = 0; t < nsteps; ++t) {
+        a.src = c->fbuf(c->par);
+        a.dst = c->fbuf(1 - c->par);
+        a.clk_in = c->clock() + c->par;
+        a.clk_out = c->clock() + (1 - c->par);
+        hipError_t e = launch_step_prec(c, a);
+        if (e != hipSuccess) return fail(SCLBM_EHIP, "step kernel: %s", hipGetErrorString(e));
+        c->par ^= 1;
+        c->n += 1;
+    }
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_get_step(const sclbm_ctx *c, int64_t *step) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!step) return fail(SCLBM_EINVAL, "null step pointer");
+    *step = c->n;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_fields(sclbm_ctx *c, int32_t box, double *rho_a, double *rho_b, double *u) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, false))) return st;
+    if (!rho_a || !rho_b) return fail(SCLBM_EINVAL, "rho_a and rho_b must not be NULL");
+    return fields_into(c, box, rho_a, rho_b, u);
+}
+
+sclbm_status sclbm_totals(sclbm_ctx *c, int32_t box, double mass[2], double momentum[3]) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, false))) return st;
+    if (!mass || !momentum) return fail(SCLBM_EINVAL, "null output");
+    if ((st = launch_stats(c, box))) return st;
+    double r[NSTAT];
+    HIP_TRY(hipMemcpyAsync(r, c->result(), sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    mass[0] = r[0];
+    mass[1] = r[1];
+    momentum[0] = r[2];
+    momentum[1] = r[3];
+    momentum[2] = r[4];
+    if (r[15] != 0.0) return fail(SCLBM_EUNSTABLE, "%.0f nodes with NaN/Inf or non-positive density", r[15]);
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_droplet_moments(sclbm_ctx *c, int32_t box, double *dev_out10) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, false))) return st;
+    if (!dev_out10) return fail(SCLBM_EINVAL, "null output");
+    if ((st = launch_stats(c, box))) return st;
+    HIP_TRY(hipMemcpyAsync(dev_out10, c->result() + 5, 10 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_droplet_from_moments(const double mom[10], const double center[3], int64_t step,
+                                        sclbm_droplet_stats *out) {
+    if (!mom || !center || !out) return fail(SCLBM_EINVAL, "null argument");
+    std::memset(out, 0, sizeof *out);
+    out->step = step;
+    const double S0 = mom[0];
+    out->volume = S0;
+    if (!(S0 > 0.0)) {
+        for (int k = 0; k < 3; ++k) out->com[k] = center[k];
+        return SCLBM_OK;
+    }
+    const double m1[3] = {mom[1] / S0, mom[2] / S0, mom[3] / S0};
+    for (int k = 0; k < 3; ++k) out->com[k] = center[k] + m1[k];
+    // S2 about the centre -> covariance about the centre of mass
+    out->cov[0] = mom[4] / S0 - m1[0] * m1[0];
+    out->cov[1] = mom[5] / S0 - m1[0] * m1[1];
+    out->cov[2] = mom[6] / S0 - m1[0] * m1[2];
+    out->cov[3] = mom[7] / S0 - m1[1] * m1[1];
+    out->cov[4] = mom[8] / S0 - m1[1] * m1[2];
+    out->cov[5] = mom[9] / S0 - m1[2] * m1[2];
+    double lam[3];
+    sym3_eigenvalues(out->cov, lam);
+    for (int k = 0; k < 3; ++k) out->semi_axes[k] = std::sqrt(5.0 * std::max(0.0, lam[k]));
+    const double s = out->semi_axes[0] + out->semi_axes[2];
+    out->deformation = s > 0.0 ? (out->semi_axes[0] - out->semi_axes[2]) / s : 0.0;
+    out->r_eq = std::cbrt(3.0 * S0 / (4.0 * M_PI));
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_droplet(sclbm_ctx *c, int32_t box, sclbm_droplet_stats *out) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, false))) return st;
+    if (!out) return fail(SCLBM_EINVAL, "null output");
+    if ((st = launch_stats(c, box))) return st;
+    double r[NSTAT];
+    HIP_TRY(hipMemcpyAsync(r, c->result(), sizeof r, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return sclbm_droplet_from_moments(r + 5, c->geom.xc, c->n, out);
+}
+
+sclbm_status sclbm_velocity_error(sclbm_ctx *c, int32_t box, const double A[9], double *e0) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, false))) return st;
+    if (!A || !e0) return fail(SCLBM_EINVAL, "null argument");
+    double *d = c->diag();
+    if ((st = fields_into(c, box, d, d + c->N, d + 2 * c->N))) return st;
+    Mat3 m;
+    for (int k = 0; k < 9; ++k) m.a[k] = A[k];
+    hipLaunchKernelGGL(k_e0, dim3(NRED_BLOCKS), dim3(NRED_THREADS), 0, c->stream, d + 2 * c->N, c->geom, m,
+                       c->partial());
+    HIP_LAUNCHED();
+    double r[2];
+    if ((st = reduce_final<2>(c, NRED_BLOCKS, r))) return st;
+    if (!(r[1] > 0.0)) return fail(SCLBM_EINVAL, "the imposed flow is zero on this box");
+    *e0 = std::sqrt(r[0]) / std::sqrt(r[1]);
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_state_bytes(const sclbm_ctx *c, size_t *bytes) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!bytes) return fail(SCLBM_EINVAL, "null bytes pointer");
+    *bytes = 64 + c->lay.fbytes;
+    return SCLBM_OK;
+}
+
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int64_t n;
+    int32_t nx, ny, nz, nbox, prec, bc;
+    int64_t fbytes;
+};
+static_assert(sizeof(CkptHeader) <= 64, "header");
+}  // namespace
+
+sclbm_status sclbm_save(sclbm_ctx *c, void *host_buf, size_t bytes) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!host_buf) return fail(SCLBM_EINVAL, "null buffer");
+    if (bytes < 64 + c->lay.fbytes) return fail(SCLBM_ESIZE, "buffer %zu < %zu", bytes, 64 + c->lay.fbytes);
+    CkptHeader h{};
+    std::memcpy(h.magic, "SCLBMCK1", 8);
+    h.n = c->n;
+    h.nx = c->cfg.nx;
+    h.ny = c->cfg.ny;
+    h.nz = c->cfg.nz;
+    h.nbox = c->cfg.nbox;
+    h.prec = c->cfg.prec;
+    h.bc = c->cfg.bc;
+    h.fbytes = int64_t(c->lay.fbytes);
+    std::memset(host_buf, 0, 64);
+    std::memcpy(host_buf, &h, sizeof h);
+    HIP_TRY(hipMemcpyAsync(static_cast<char *>(host_buf) + 64, c->fbuf(c->par), c->lay.fbytes, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_load(sclbm_ctx *c, const void *host_buf, size_t bytes) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!host_buf) return fail(SCLBM_EINVAL, "null buffer");
+    if (bytes < 64) return fail(SCLBM_ESIZE, "buffer too small");
+    CkptHeader h;
+    std::memcpy(&h, host_buf, sizeof h);
+    if (std::memcmp(h.magic, "SCLBMCK1", 8) != 0) return fail(SCLBM_EINVAL, "not a checkpoint");
+    if (h.nx != c->cfg.nx || h.ny != c->cfg.ny || h.nz != c->cfg.nz || h.nbox != c->cfg.nbox ||
+        h.prec != c->cfg.prec || h.bc != c->cfg.bc || h.fbytes != int64_t(c->lay.fbytes))
+        return fail(SCLBM_EINVAL, "checkpoint was written for a different configuration");
+    if (bytes < 64 + c->lay.fbytes) return fail(SCLBM_ESIZE, "buffer truncated");
+    HIP_TRY(hipMemcpyAsync(c->fbuf(0), static_cast<const char *>(host_buf) + 64, c->lay.fbytes, hipMemcpyHostToDevice,
+                           c->stream));
+    int64_t clk[2] = {h.n, h.n};
+    HIP_TRY(hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->par = 0;
+    c->n = h.n;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (tile_rows != 2 && tile_rows != 4 && tile_rows != 8) return fail(SCLBM_EINVAL, "tile_rows must be 2, 4 or 8");
+    if (zchunk < 1) return fail(SCLBM_EINVAL, "zchunk must be >= 1");
+    c->tile_rows = tile_rows;
+    c->zchunk = std::min<int32_t>(zchunk, c->cfg.nz);
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_get_launch(const sclbm_ctx *c, int32_t *tile_rows, int32_t *zchunk) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (tile_rows) *tile_rows = c->tile_rows;
+    if (zchunk) *zchunk = c->zchunk;
+    return SCLBM_OK;
+}
+
+}  // extern "C"

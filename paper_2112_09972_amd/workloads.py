@@ -1,0 +1,168 @@
+"""Seeded synthetic inputs for the droplet boxes: model constants, velocity-gradient
+tables and the box configurations used by the tests and the benchmark.
+
+None of the method's arithmetic lives here — only inputs: numbers that configure
+the model and the A(t) histories that drive the ghost nodes.  The paper drives
+its boxes with velocity gradients of tracers in a turbulence simulation (Sec. 3,
+Fig. 2); that data set is not available, so an Ornstein-Uhlenbeck process with
+the same role (a smooth, traceless, random A(t)) stands in for it.
+
+Constants that the paper does not print were measured with the FP64 CPU oracle
+by ``tests/golden/calibrate.py`` (values in ``tests/golden/calibration.json``):
+the coupling G_AB that gives a flat-interface density ratio of 0.04 at tau = 1,
+the surface tension from the Laplace law, and the solvent densities in
+equilibrium with a droplet of radius R.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+TAU = 1.0            # both components (Table 1 uses tau = 1)
+RHO_HI = 1.0         # droplet-phase density of A at initialisation
+RHO_LO = 0.04        # solvent-phase density of A at initialisation
+WIDTH = 2.0          # tanh width of the initial interface
+G_AB = 1.6417        # flat interface: minority/majority = 0.04
+SIGMA = 0.089909     # Laplace law, tau = 1, G_AB above
+FAR_FIELD_A = (0.05375933605501905, 0.04041950406144379)    # rho_A far field = a/R_eq + b
+FAR_FIELD_B = (-0.235900760858221, 1.0375176769822088)      # rho_B far field = a/R_eq + b
+CS = 1.0 / math.sqrt(3.0)
+MACH_MAX = 0.2       # Sec. 4: the velocity scale keeps Ma <= 0.2
+
+
+def eta_s(tau: float = TAU) -> float:
+    """Dynamic viscosity of the solvent: (rho_A + rho_B) nu with nu = (tau - 1/2)/3 (Sec. 2 Eq. 10)."""
+    return (RHO_HI + RHO_LO) * (tau - 0.5) / 3.0
+
+
+def ghost_densities(radius: float):
+    """Ghost densities (A, B) in equilibrium with a droplet of the given radius."""
+    return (FAR_FIELD_A[0] / radius + FAR_FIELD_A[1], FAR_FIELD_B[0] / radius + FAR_FIELD_B[1])
+
+
+def shear_rate_for_ca(ca: float, radius: float, tau: float = TAU) -> float:
+    """gamma with Ca = eta_s R gamma / sigma (Sec. 2 Eq. 3)."""
+    return ca * SIGMA / (eta_s(tau) * radius)
+
+
+def capillary(A, radius: float, tau: float = TAU) -> float:
+    """Ca = eta_s R ||A||_inf / sigma with the entry-wise maximum norm (Sec. 2 Eq. 3)."""
+    return eta_s(tau) * radius * float(np.max(np.abs(np.asarray(A)))) / SIGMA
+
+
+def simple_shear(gamma: float) -> np.ndarray:
+    """u = (gamma z, 0, 0): A[0][2] = gamma, row-major 9 values."""
+    A = np.zeros(9)
+    A[2] = gamma
+    return A
+
+
+def corner_speed_bound(A, n) -> float:
+    """Upper bound of |A (x - x_c)| over the ghost layer of an n^3 box: the maximum
+    over the corners of [-1, n]^3 (|A d| is convex in d)."""
+    A = np.asarray(A, dtype=np.float64).reshape(-1, 3, 3)
+    h = (n + 1) / 2.0
+    corners = np.array([[sx, sy, sz] for sx in (-h, h) for sy in (-h, h) for sz in (-h, h)])
+    v = np.einsum("tij,cj->tci", A, corners)
+    return float(np.sqrt((v * v).sum(-1)).max())
+
+
+def ou_samples(seed: int, nsamples: int, stride: int = 50, corr_time: float = 2000.0) -> np.ndarray:
+    """Nine independent unit-variance OU components sampled every `stride` steps
+    with the exact update a_{k+1} = e^{-S/T} a_k + sqrt(1 - e^{-2S/T}) xi_k,
+    projected to trace zero.  Shape (nsamples, 3, 3)."""
+    rng = np.random.default_rng(seed)
+    decay = math.exp(-stride / corr_time)
+    kick = math.sqrt(1.0 - decay * decay)
+    a = np.empty((nsamples, 9))
+    a[0] = rng.standard_normal(9)
+    for k in range(1, nsamples):
+        a[k] = decay * a[k - 1] + kick * rng.standard_normal(9)
+    A = a.reshape(nsamples, 3, 3)
+    tr = np.trace(A, axis1=1, axis2=2)
+    return A - tr[:, None, None] * np.eye(3)[None] / 3.0
+
+
+def per_step_table(samples: np.ndarray, stride: int, nsteps: int) -> np.ndarray:
+    """Per-step rows from samples held every `stride` steps, linearly interpolated
+    between consecutive samples.  Shape (nsteps, 9)."""
+    t = np.arange(nsteps) / stride
+    k = np.minimum(np.floor(t).astype(int), samples.shape[0] - 2)
+    frac = (t - k)[:, None, None]
+    rows = samples[k] * (1.0 - frac) + samples[k + 1] * frac
+    return rows.reshape(nsteps, 9)
+
+
+def strain_rms(rows: np.ndarray) -> float:
+    """Time rms of sqrt(2 S_ij S_ij), S the symmetric part (Sec. 2 Eq. 2)."""
+    A = np.asarray(rows).reshape(-1, 3, 3)
+    S = 0.5 * (A + A.transpose(0, 2, 1))
+    return float(np.sqrt(np.mean(2.0 * np.sum(S * S, axis=(1, 2)))))
+
+
+def ou_gradient_table(seed: int, n: int, nsteps: int, mach: float = MACH_MAX, stride: int = 50,
+                      corr_time: float = 2000.0) -> np.ndarray:
+    """OU-driven per-step table for an n^3 box, scaled so that the largest ghost
+    speed over the whole history is `mach` * c_s."""
+    nsamp = nsteps // stride + 2
+    raw = per_step_table(ou_samples(seed, nsamp, stride, corr_time), stride, nsteps)
+    scale = mach * CS / corner_speed_bound(raw, n)
+    return raw * scale
+
+
+@dataclass
+class BoxCase:
+    """One synthetic workload."""
+    name: str
+    n: int
+    radius: float
+    prec: str
+    nsteps: int
+    nbox: int = 1
+    bc: str = "ghost"
+    tau: float = TAU
+    seeds: tuple = ()
+    stride: int = 50
+    tables: list = field(default_factory=list)
+    ca: float = 0.0
+
+    @property
+    def rho_b(self):
+        return ghost_densities(self.radius)
+
+    @property
+    def nodes(self) -> int:
+        return self.n ** 3 * self.nbox
+
+
+def case_c1() -> BoxCase:
+    """32^3, R = 6, tau = 1, steady simple shear at Ca = 0.1, FP64, 1000 steps."""
+    c = BoxCase("c1_32cube_shear_f64", 32, 6.0, "f64", 1000, ca=0.1)
+    c.tables = [np.tile(simple_shear(shear_rate_for_ca(0.1, 6.0)), (c.nsteps, 1))]
+    return c
+
+
+def case_c2(nsteps: int = 20000) -> BoxCase:
+    """128^3, R = 16, FP32, OU A(t) (seed 2), 20000 steps."""
+    c = BoxCase("c2_128cube_ou_f32", 128, 16.0, "f32", nsteps, seeds=(2,))
+    c.tables = [ou_gradient_table(2, 128, nsteps)]
+    return c
+
+
+def case_c3(prec: str = "f16dev", nsteps: int = 10000) -> BoxCase:
+    """256^3, R = 32, OU A(t) (seed 3), 10000 steps, deviation storage."""
+    c = BoxCase("c3_256cube_ou_" + prec, 256, 32.0, prec, nsteps, seeds=(3,))
+    c.tables = [ou_gradient_table(3, 256, nsteps)]
+    return c
+
+
+def case_c4(nsteps: int = 20000, nbox: int = 64) -> BoxCase:
+    """64 boxes of 64^3, R = 10, each with its own OU A(t) (seeds 1000..1063), the
+    peak ghost Mach number spread linearly over the boxes, FP32."""
+    seeds = tuple(range(1000, 1000 + nbox))
+    c = BoxCase("c4_64x64cube_ou_f32", 64, 10.0, "f32", nsteps, nbox=nbox, seeds=seeds)
+    machs = np.linspace(0.04, MACH_MAX, nbox)
+    c.tables = [ou_gradient_table(s, 64, nsteps, mach=float(m)) for s, m in zip(seeds, machs)]
+    return c

@@ -1,0 +1,92 @@
+"""C-ABI checks that need no GPU: the library loads, exports every call that
+include/sclbm.h declares, validates configurations, and its host-only droplet
+analysis (closed-form 3x3 eigenvalues) matches the oracle's on known moments."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "sclbm.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sclbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_call():
+    import ctypes
+    import paper_2112_09972_amd as sc
+    lib = ctypes.CDLL(sc.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(sc.EXPORTS) == names
+
+
+def cfg(**kw):
+    import paper_2112_09972_amd as sc
+    base = dict(nx=32, ny=32, nz=32, nbox=1, bc=1, prec=0, table_len=10, g_ab=1.64, mach_max=0.0)
+    base.update(kw)
+    tau = base.pop("tau", (1.0, 1.0))
+    rho_b = base.pop("rho_b", (0.04, 1.0))
+    import ctypes
+    return sc.sclbm_config(tau=(ctypes.c_double * 2)(*tau), rho_b=(ctypes.c_double * 2)(*rho_b), **base)
+
+
+def test_workspace_size():
+    import paper_2112_09972_amd as sc
+    b64 = sc.sclbm_workspace_bytes(cfg())
+    b32 = sc.sclbm_workspace_bytes(cfg(prec=1))
+    pop64 = 2 * 19 * 32 ** 3 * 8
+    assert b64 >= 2 * pop64
+    assert b64 - b32 == 2 * (pop64 // 2)
+    b16 = sc.sclbm_workspace_bytes(cfg(prec=2, nbox=3))
+    assert b16 >= 2 * 3 * 2 * 19 * 32 ** 3 * 2
+
+
+@pytest.mark.parametrize("bad", [dict(nx=2), dict(nbox=0), dict(bc=7), dict(prec=9), dict(tau=(0.5, 1.0)),
+                                 dict(rho_b=(0.0, 1.0)), dict(table_len=0), dict(mach_max=-1.0),
+                                 dict(g_ab=float("nan"))])
+def test_invalid_configs_rejected(bad):
+    import paper_2112_09972_amd as sc
+    with pytest.raises(sc.SclbmError) as ei:
+        sc.sclbm_workspace_bytes(cfg(**bad))
+    assert ei.value.status == sc.SCLBM_EINVAL
+    assert "invalid config" in sc.sclbm_last_error()
+
+
+@pytest.mark.parametrize("axes,th", [((10.0, 8.0, 6.0), 0.0), ((9.0, 7.0, 5.0), 0.6), ((6.0, 6.0, 6.0), 0.0),
+                                     ((7.0, 7.0, 4.0), 1.1)])
+def test_host_droplet_analysis_matches_oracle(axes, th):
+    import paper_2112_09972_amd as sc
+    n = 36
+    c = np.array([(n - 1) / 2.0] * 3)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    d = np.stack([x - c[0] - 0.3, y - c[1] + 0.2, z - c[2]]).reshape(3, -1)
+    Rm = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    d = Rm.T @ d
+    inside = (d[0] / axes[0]) ** 2 + (d[1] / axes[1]) ** 2 + (d[2] / axes[2]) ** 2 < 1.0
+    ra = np.where(inside, 1.0, 0.04).reshape(n, n, n)
+    rb = 1.04 - ra
+    mom = oracle.droplet_moments(ra, rb, c)
+    ref = oracle.droplet_stats_from_moments(mom, c)
+    got = sc.sclbm_droplet_from_moments(mom, c, 7)
+    assert got["step"] == 7
+    assert np.allclose(got["semi_axes"], ref["semi_axes"], rtol=1e-10, atol=1e-12)
+    assert abs(got["deformation"] - ref["deformation"]) < 1e-10
+    assert np.allclose(got["com"], ref["com"], rtol=0, atol=1e-12)
+    assert abs(got["r_eq"] - ref["r_eq"]) < 1e-12
+
+
+def test_empty_droplet():
+    import paper_2112_09972_amd as sc
+    got = sc.sclbm_droplet_from_moments(np.zeros(10), [1.0, 2.0, 3.0])
+    assert got["volume"] == 0.0 and np.all(got["semi_axes"] == 0.0)
+    assert np.allclose(got["com"], [1, 2, 3])
