@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--launch", type=str, default="", help="tile_rows,zchunk")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
@@ -89,6 +91,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_reference:
+        n = 1 << 28  # 2^28 FP32 = 1 GiB
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes_read": 4 * n, "copy_reference_bytes_written": 4 * n, "launches": 5}))
+        return
     import paper_2112_09972_amd as sc
     global wl
     from paper_2112_09972_amd import workloads as wl

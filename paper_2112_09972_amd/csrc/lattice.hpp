@@ -42,6 +42,17 @@ __host__ __device__ constexpr R w_of(int i) {
 // rounding after 500 steps of the droplet box).
 // The deviation formats hold d_i = f_i - w_i rho_ref in 16 bits with FP32
 // arithmetic; the reference density of each component is a context constant.
+// Raw buffer access (CDNA buffer instructions): a 128-bit descriptor per
+// population array in SGPRs, a uniform byte offset per direction (SGPR) and one
+// 32-bit byte offset per lane.  Word 3 = 0x00020000 is the raw 32-bit-element
+// layout of the gfx9 family.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000);
+}
+
 template <int P>
 struct Prec;
 template <>
@@ -51,6 +62,12 @@ struct Prec<SCLBM_F64> {
     using R = double;
     static __device__ __forceinline__ W load(const S *p, R /*wref*/) { return *p; }
     static __device__ __forceinline__ void store(S *p, R v, R /*wref*/) { *p = v; }
+    static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R /*wref*/) {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R /*wref*/) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, vo, so, 0);
+    }
 };
 template <>
 struct Prec<SCLBM_F32> {
@@ -59,6 +76,12 @@ struct Prec<SCLBM_F32> {
     using R = double;
     static __device__ __forceinline__ W load(const S *p, R /*wref*/) { return *p; }
     static __device__ __forceinline__ void store(S *p, R v, R /*wref*/) { *p = float(v); }
+    static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R /*wref*/) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R /*wref*/) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, float(v)), r, vo, so, 0);
+    }
 };
 template <>
 struct Prec<SCLBM_F16DEV> {
@@ -67,6 +90,14 @@ struct Prec<SCLBM_F16DEV> {
     using R = float;
     static __device__ __forceinline__ W load(const S *p, R wref) { return wref + __half2float(*p); }
     static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2half_rn(v - wref); }
+    static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {
+        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+        return wref + __half2float(__builtin_bit_cast(__half, b));
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v - wref)), r, vo,
+                                              so, 0);
+    }
 };
 template <>
 struct Prec<SCLBM_BF16DEV> {
@@ -75,6 +106,14 @@ struct Prec<SCLBM_BF16DEV> {
     using R = float;
     static __device__ __forceinline__ W load(const S *p, R wref) { return wref + __bfloat162float(*p); }
     static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2bfloat16(v - wref); }
+    static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {
+        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+        return wref + __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(v - wref)), r, vo,
+                                              so, 0);
+    }
 };
 
 inline size_t elem_bytes(int prec) {

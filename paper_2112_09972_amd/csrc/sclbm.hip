@@ -68,6 +68,11 @@ bool config_ok(const sclbm_config *c, std::string &why) {
     if (c->table_len < 0) { why = "table_len must be >= 0"; return false; }
     const double nodes = double(c->nx) * c->ny * c->nz * c->nbox;
     if (nodes * 2 * Q * elem_bytes(c->prec) > 250e9) { why = "populations exceed 250 GB"; return false; }
+    // the step kernel addresses one component of one box through a raw buffer (32-bit byte offsets)
+    if (double(c->nx) * c->ny * c->nz * Q * elem_bytes(c->prec) >= 4294901760.0) {
+        why = "one box's populations of one component exceed 4 GiB";
+        return false;
+    }
     return true;
 }
 
@@ -136,7 +141,12 @@ template <int P, int TY>
 hipError_t launch_step_ty(sclbm_ctx *c, const StepArgs &a) {
     dim3 block(64, TY, 1);
     dim3 grid((c->cfg.nx + 63) / 64, (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
-    hipLaunchKernelGGL((k_step<P, TY>), grid, block, 0, c->stream, a);
+    // register budget: two waves per SIMD (up to 256 VGPRs); a tighter budget spills
+    constexpr int WAVES = 2;
+    if (c->cfg.bc == SCLBM_BC_GHOST)
+        hipLaunchKernelGGL((k_step<P, TY, true, WAVES>), grid, block, 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_step<P, TY, false, WAVES>), grid, block, 0, c->stream, a);
     return hipGetLastError();
 }
 
@@ -431,7 +441,6 @@ sclbm_status sclbm_step(sclbm_ctx *c, int64_t nsteps) {
     a.nz = c->cfg.nz;
     a.zchunk = c->zchunk;
     a.nzc = (c->cfg.nz + c->zchunk - 1) / c->zchunk;
-    a.ghost = ghost ? 1 : 0;
     for (int s = 0; s < 2; ++s) {
         a.tau[s] = c->cfg.tau[s];
         a.omega[s] = 1.0 / c->cfg.tau[s];

@@ -13,11 +13,23 @@
 // row, so every population stream is a coalesced 64-wide access) and marches
 // along z through a chunk of planes.  The force at plane z needs the densities
 // of planes z-1, z, z+1 including a one-node ring around the tile; those
-// densities live in a 4-slot rolling buffer in LDS.  Each plane's populations
-// are loaded once into registers, held for one plane while the next plane's
-// densities arrive, then collided and stored.  Ring densities (and the two
-// chunk-end planes) are recomputed from HBM/L2 rather than exchanged between
-// workgroups, so a step is a single launch with no grid-wide synchronisation.
+// densities live in a 4-slot rolling buffer in LDS.  Per plane the workgroup
+// first sums the populations of its nodes and of the ring into densities
+// (density pass), then, one plane behind, reads its own nodes' populations a
+// second time, collides them and stores them.  Holding no populations across
+// the barrier keeps register use low enough for two waves per SIMD.  Ring
+// densities (and the two chunk-end planes) are recomputed rather than exchanged
+// between workgroups, so a step is a single launch with no grid-wide
+// synchronisation.
+//
+// Instruction economy (the kernel issues about as many VALU instructions as it
+// can hide behind HBM traffic): populations are handled in opposite-velocity
+// pairs (c_{2k} = -c_{2k-1}), which shares the symmetric and antisymmetric parts
+// of the equilibrium and of the force stencil; the velocity shift
+// tau_s F_s / rho_s = -G tau_s sum_i w_i rho_s'(x + c_i) c_i needs no division;
+// every access goes through raw-buffer instructions with one 32-bit per-lane
+// byte offset.  In ghost mode a push whose destination lies outside the box gets
+// an out-of-range offset, which the buffer unit discards, instead of a branch.
 #pragma once
 
 #include "lattice.hpp"
@@ -34,7 +46,6 @@ struct StepArgs {
     int64_t table_len;
     int64_t nnode;            // nodes per box
     int nx, ny, nz, nzc, zchunk;
-    int ghost;
     double omega[2];          // 1/tau
     double tau[2];
     double g;                 // G_AB
@@ -43,115 +54,91 @@ struct StepArgs {
     double xc[3];             // box centre
 };
 
-// Density of both components at an in-box node (x,y,z) of one box.
-template <int P>
-__device__ __forceinline__ void node_density(const typename Prec<P>::S *f, int64_t N, int64_t idx,
-                                             const typename Prec<P>::R wref[2][Q],
-                                             typename Prec<P>::R out[2]) {
-    using R = typename Prec<P>::R;
+// Byte offset the buffer unit treats as out of range (every population array
+// of one component and box is smaller; checked on the host).
+constexpr uint32_t kOOB = 0xFFFFFFF0u;
+
+// Density of one component from its 19 populations, summed in opposite pairs.
+// The own-node and ring paths both use this so that a node's density does not
+// depend on which tile computed it.
+template <typename R, typename W>
+__device__ __forceinline__ R pair_density(const W (&f)[Q]) {
+    R r = R(f[0]);
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        R acc = R(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) acc += R(Prec<P>::load(f + (int64_t)(s * Q + i) * N + idx, wref[s][i]));
-        out[s] = acc;
-    }
+    for (int k = 1; k < Q; k += 2) r += R(f[k]) + R(f[k + 1]);
+    return r;
 }
 
-template <int P, int TY>
-__global__ __launch_bounds__(64 * TY) void k_step(StepArgs a) {
+// Equilibrium bracket rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2) of Sec. 2 Eq. 8 for
+// both members of the pair (c, -c), as sym +- asym; aa = rho (1 - 3/2 u^2).
+template <typename R>
+__device__ __forceinline__ void eq_pair(R cu, R aa, R rho3, R rho45, R &plus, R &minus) {
+    const R sym = (rho45 * cu) * cu + aa;
+    const R asym = rho3 * cu;
+    plus = sym + asym;
+    minus = sym - asym;
+}
+
+template <int P, int TY, bool GHOST, int WAVES>
+__global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
     using S = typename Prec<P>::S;
     using W = typename Prec<P>::W;
     using R = typename Prec<P>::R;
     constexpr int LW = 66;  // 64 + ring
+    constexpr uint32_t EB = sizeof(S);
     __shared__ R lds[4][2][TY + 2][LW];
 
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = ly * 64 + lx;
-    const int x0 = blockIdx.x * 64, y0 = blockIdx.y * TY;
-    const int box = blockIdx.z / a.nzc;
-    const int zs = (blockIdx.z % a.nzc) * a.zchunk;
+    // XCD-aware tile order: workgroups are dispatched round-robin over the 8
+    // XCDs by linear id, so give XCD k one contiguous run of tiles (x fastest,
+    // then y, then z-chunk and box).  Neighbouring tiles then share an L2 for
+    // their ring re-reads and for the partial cache lines of shifted stores.
+    const uint32_t nbx = gridDim.x, nby = gridDim.y;
+    const uint32_t nb = nbx * nby * gridDim.z;
+    const uint32_t lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
+    const uint32_t q8 = nb / 8, r8 = nb % 8, xcd = lin % 8, k8 = lin / 8;
+    const uint32_t tile = xcd < r8 ? xcd * (q8 + 1) + k8 : r8 * (q8 + 1) + (xcd - r8) * q8 + k8;
+    const int bx = int(tile % nbx), by = int((tile / nbx) % nby), bz = int(tile / (nbx * nby));
+    const int x0 = bx * 64, y0 = by * TY;
+    const int box = bz / a.nzc;
+    const int zs = (bz % a.nzc) * a.zchunk;
     const int ze = min(zs + a.zchunk, a.nz);
     const int x = x0 + lx, y = y0 + ly;
     const bool valid = (x < a.nx) && (y < a.ny);
     const int tw = min(64, a.nx - x0), th = min(TY, a.ny - y0);  // valid tile extent
-    const int64_t N = a.nnode;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const uint32_t N = uint32_t(a.nnode);
+    const uint32_t nxy = uint32_t(nx) * uint32_t(ny);
+    const uint32_t plane_bytes = N * EB;  // one direction of one component
+
+    // one descriptor per component and buffer; 19 N elements each (< 4 GiB, checked on the host)
+    const uint32_t comp_bytes = uint32_t(Q) * plane_bytes;
     const S *src = (const S *)a.src + (int64_t)box * 2 * Q * N;
     S *dst = (S *)a.dst + (int64_t)box * 2 * Q * N;
+    const rsrc_t rs[2] = {make_rsrc(src, comp_bytes), make_rsrc(src + (int64_t)Q * N, comp_bytes)};
+    const rsrc_t rd[2] = {make_rsrc(dst, comp_bytes), make_rsrc(dst + (int64_t)Q * N, comp_bytes)};
 
     const int64_t n = *a.clk_in;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && tid == 0) *a.clk_out = n + 1;
+    if (lin == 0 && tid == 0) *a.clk_out = n + 1;
 
-    R wref[2][Q];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int i = 0; i < Q; ++i) wref[s][i] = w_of<R>(i) * R(a.rho_ref[s]);
-
-    const R om[2] = {R(a.omega[0]), R(a.omega[1])};
-    const R tau[2] = {R(a.tau[0]), R(a.tau[1])};
-    const R G = R(a.g);
+    const R rref[2] = {R(a.rho_ref[0]), R(a.rho_ref[1])};
     const R rhob[2] = {R(a.rho_b[0]), R(a.rho_b[1])};
-
-    R Am[9];
-    if (a.ghost) {
-        const double *row = a.atab + ((int64_t)box * a.table_len + (n - a.tab_first[box])) * 9;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Am[k] = R(row[k]);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) Am[k] = R(0);
-    }
-
-    W fprev[2][Q], fcur[2][Q];
-    R rho_p[2] = {R(0), R(0)}, j_p[2][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
     const int ringN = 2 * (tw + 2) + 2 * th;
     const int nplanes = (ze - zs) + 2;
 
     for (int k = 0; k < nplanes; ++k) {
         const int z = zs - 1 + k;
         const int slot = k & 3;
-        // ---- 1. own node of plane z: populations into registers, moments ----
-        R rho_c[2] = {R(0), R(0)}, j_c[2][3] = {{R(0), R(0), R(0)}, {R(0), R(0), R(0)}};
-        if (valid) {
-            int zz = z;
-            bool inside = (z >= 0) && (z < nz);
-            if (!inside && !a.ghost) {
-                zz = (z + nz) % nz;
-                inside = true;
-            }
-            if (inside) {
-                const int64_t idx = ((int64_t)zz * ny + y) * nx + x;
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) fcur[s][i] = Prec<P>::load(src + (int64_t)(s * Q + i) * N + idx, wref[s][i]);
-                    R r = R(0), jx = R(0), jy = R(0), jz = R(0);
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        const R v = R(fcur[s][i]);
-                        r += v;
-                        if (cx_of(i)) jx += R(cx_of(i)) * v;
-                        if (cy_of(i)) jy += R(cy_of(i)) * v;
-                        if (cz_of(i)) jz += R(cz_of(i)) * v;
-                    }
-                    rho_c[s] = r;
-                    j_c[s][0] = jx;
-                    j_c[s][1] = jy;
-                    j_c[s][2] = jz;
-                }
-            } else {
-                rho_c[0] = rhob[0];
-                rho_c[1] = rhob[1];
-            }
-            lds[slot][0][ly + 1][lx + 1] = rho_c[0];
-            lds[slot][1][ly + 1][lx + 1] = rho_c[1];
-        }
-        // ---- 2. ring densities of plane z ----
-        for (int r = tid; r < ringN; r += 64 * TY) {
+        // ---- 1. densities of plane z: the own node, then the ring ----
+        for (int r = tid - 64 * TY; r < ringN; r += 64 * TY) {
             int sx, sy;
-            if (r < tw + 2) {
+            bool work = true;
+            if (r < 0) {
+                sx = lx + 1;
+                sy = ly + 1;
+                work = valid;
+            } else if (r < tw + 2) {
                 sx = r;
                 sy = 0;
             } else if (r < 2 * (tw + 2)) {
@@ -164,17 +151,26 @@ __global__ __launch_bounds__(64 * TY) void k_step(StepArgs a) {
                 sx = tw + 1;
                 sy = r - 2 * (tw + 2) - th + 1;
             }
+            if (!work) continue;
             int gx = x0 - 1 + sx, gy = y0 - 1 + sy, gz = z;
             bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-            R rr[2];
-            if (!inside && !a.ghost) {
-                gx = (gx + nx) % nx;
-                gy = (gy + ny) % ny;
-                gz = (gz + nz) % nz;
+            if (!GHOST) {
+                gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
+                gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
+                gz = gz < 0 ? gz + nz : (gz >= nz ? gz - nz : gz);
                 inside = true;
             }
+            R rr[2];
             if (inside) {
-                node_density<P>(src, N, ((int64_t)gz * ny + gy) * nx + gx, wref, rr);
+                const uint32_t vo = (uint32_t(gz) * nxy + uint32_t(gy) * uint32_t(nx) + uint32_t(gx)) * EB;
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    W f[Q];
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                        f[i] = Prec<P>::bload(rs[s], vo + uint32_t(i) * plane_bytes, 0, w_of<R>(i) * rref[s]);
+                    rr[s] = pair_density<R>(f);
+                }
             } else {
                 rr[0] = rhob[0];
                 rr[1] = rhob[1];
@@ -183,92 +179,164 @@ __global__ __launch_bounds__(64 * TY) void k_step(StepArgs a) {
             lds[slot][1][sy][sx] = rr[1];
         }
         __syncthreads();
+        if (k < 2) continue;
 
-        // ---- 3. collide plane z-1 and push ----
-        if (k >= 2 && valid) {
-            const int zc = z - 1;
-            // pair force, Eq. 7: F_s = -G rho_s sum_i w_i rho_s'(x + c_i) c_i
-            R F[2][3];
+        // ---- 2. collide plane z-1 and push ----
+        const int zc = z - 1;
+        const uint32_t node = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
+        const uint32_t vo = node * EB;
+        const bool xlo = x == 0, xhi = x == nx - 1, ylo = y == 0, yhi = y == ny - 1;
+        const bool zlo = zc == 0, zhi = zc == nz - 1;
+        if (valid) {
+            // populations of the own node (second read of this plane)
+            W f[2][Q];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    f[s][i] = Prec<P>::bload(rs[s], vo + uint32_t(i) * plane_bytes, 0, w_of<R>(i) * rref[s]);
+            // moments, Eq. 6: density and momentum from pair sums and differences
+            R rho[2], j[2][3];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                R d[10];
+#pragma unroll
+                for (int p = 1; p <= 9; ++p) d[p] = R(f[s][2 * p - 1]) - R(f[s][2 * p]);
+                rho[s] = pair_density<R>(f[s]);
+                j[s][0] = d[1] + d[4] + d[5] + d[6] + d[7];
+                j[s][1] = d[2] + d[4] - d[5] + d[8] + d[9];
+                j[s][2] = d[3] + d[6] - d[7] + d[8] - d[9];
+            }
+            // pair force, Eq. 7, as the stencil sum sig_s = sum_i w_i rho_s'(x + c_i) c_i
+            // (F_s = -G rho_s sig_s) from pair differences of the LDS densities
+            R sig[2][3];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int o = 1 - s;
-                R sx = R(0), sy = R(0), sz = R(0);
+                R e[10];
 #pragma unroll
-                for (int i = 1; i < Q; ++i) {
-                    const R nb = lds[(k - 1 + cz_of(i)) & 3][o][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)];
-                    const R wn = w_of<R>(i) * nb;
-                    if (cx_of(i)) sx += R(cx_of(i)) * wn;
-                    if (cy_of(i)) sy += R(cy_of(i)) * wn;
-                    if (cz_of(i)) sz += R(cz_of(i)) * wn;
+                for (int p = 1; p <= 9; ++p) {
+                    const int i = 2 * p - 1;
+                    const R hi = lds[(k - 1 + cz_of(i)) & 3][o][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)];
+                    const R lo = lds[(k - 1 - cz_of(i)) & 3][o][ly + 1 - cy_of(i)][lx + 1 - cx_of(i)];
+                    e[p] = hi - lo;
                 }
-                const R pre = -G * rho_p[s];
-                F[s][0] = pre * sx;
-                F[s][1] = pre * sy;
-                F[s][2] = pre * sz;
+                const R w1 = R(1) / R(18), w2 = R(1) / R(36);
+                sig[s][0] = w1 * e[1] + w2 * (e[4] + e[5] + e[6] + e[7]);
+                sig[s][1] = w1 * e[2] + w2 * (e[4] - e[5] + e[8] + e[9]);
+                sig[s][2] = w1 * e[3] + w2 * (e[6] - e[7] + e[8] - e[9]);
             }
-            // common velocity and per-component shifted equilibrium velocity
-            const R den = rho_p[0] * om[0] + rho_p[1] * om[1];
-            const R inv_den = R(1) / den;
-            const R up[3] = {(j_p[0][0] * om[0] + j_p[1][0] * om[1]) * inv_den,
-                             (j_p[0][1] * om[0] + j_p[1][1] * om[1]) * inv_den,
-                             (j_p[0][2] * om[0] + j_p[1][2] * om[1]) * inv_den};
-            const bool bx = (x == 0) || (x == nx - 1);
-            const bool by = (y == 0) || (y == ny - 1);
-            const bool bz = (zc == 0) || (zc == nz - 1);
+            // common velocity u' and shifted velocity u' + tau_s F_s / rho_s = u' - G tau_s sig_s
+            const R om0 = R(a.omega[0]), om1 = R(a.omega[1]);
+            const R inv_den = R(1) / (rho[0] * om0 + rho[1] * om1);
+            const R up[3] = {(j[0][0] * om0 + j[1][0] * om1) * inv_den, (j[0][1] * om0 + j[1][1] * om1) * inv_den,
+                             (j[0][2] * om0 + j[1][2] * om1) * inv_den};
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const R sh = tau[s] / rho_p[s];
-                const R ux = up[0] + sh * F[s][0];
-                const R uy = up[1] + sh * F[s][1];
-                const R uz = up[2] + sh * F[s][2];
+                const R om = s ? om1 : om0;
+                const R gt = R(a.g) * R(a.tau[s]);
+                const R ux = up[0] - gt * sig[s][0];
+                const R uy = up[1] - gt * sig[s][1];
+                const R uz = up[2] - gt * sig[s][2];
                 const R usq = ux * ux + uy * uy + uz * uz;
+                const R r = rho[s];
+                const R aa = r - R(1.5) * r * usq;
+                const R r3 = R(3) * r, r45 = R(4.5) * r;
+                R feq[Q];
+                feq[0] = aa;
+#pragma unroll
+                for (int p = 1; p <= 9; ++p) {
+                    const int i = 2 * p - 1;
+                    R cu = R(0);
+                    if (cx_of(i)) cu += R(cx_of(i)) * ux;
+                    if (cy_of(i)) cu += R(cy_of(i)) * uy;
+                    if (cz_of(i)) cu += R(cz_of(i)) * uz;
+                    eq_pair<R>(cu, aa, r3, r45, feq[i], feq[i + 1]);
+                }
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const R fe = equilibrium<R>(i, rho_p[s], ux, uy, uz, usq);
-                    const R fi = R(fprev[s][i]);
-                    const R p = fi - om[s] * (fi - fe);
-                    int dx = x + cx_of(i), dy = y + cy_of(i), dz = zc + cz_of(i);
-                    bool ok = true;
-                    if (a.ghost) {
-                        ok = dx >= 0 && dx < nx && dy >= 0 && dy < ny && dz >= 0 && dz < nz;
+                    const R fi = R(f[s][i]);
+                    const R pst = fi + om * (w_of<R>(i) * feq[i] - fi);
+                    uint32_t dvo;
+                    if (GHOST) {
+                        const bool out = (cx_of(i) < 0 && xlo) || (cx_of(i) > 0 && xhi) || (cy_of(i) < 0 && ylo) ||
+                                         (cy_of(i) > 0 && yhi) || (cz_of(i) < 0 && zlo) || (cz_of(i) > 0 && zhi);
+                        const int shift = cx_of(i) + cy_of(i) * nx + cz_of(i) * int(nxy);
+                        dvo = out ? kOOB : uint32_t(int(node) + shift) * EB + uint32_t(i) * plane_bytes;
                     } else {
+                        int dx = x + cx_of(i), dy = y + cy_of(i), dz = zc + cz_of(i);
                         dx = dx < 0 ? dx + nx : (dx >= nx ? dx - nx : dx);
                         dy = dy < 0 ? dy + ny : (dy >= ny ? dy - ny : dy);
                         dz = dz < 0 ? dz + nz : (dz >= nz ? dz - nz : dz);
+                        dvo = (uint32_t(dz) * nxy + uint32_t(dy) * uint32_t(nx) + uint32_t(dx)) * EB +
+                              uint32_t(i) * plane_bytes;
                     }
-                    if (ok) Prec<P>::store(dst + (int64_t)(s * Q + i) * N + ((int64_t)dz * ny + dy) * nx + dx, p, wref[s][i]);
-                }
-            }
-            // populations streaming in from ghost nodes (boundary nodes only)
-            if (a.ghost && (bx || by || bz)) {
-                const int64_t idx = ((int64_t)zc * ny + y) * nx + x;
-#pragma unroll
-                for (int i = 1; i < Q; ++i) {
-                    const int gx = x - cx_of(i), gy = y - cy_of(i), gz = zc - cz_of(i);
-                    const bool out = gx < 0 || gx >= nx || gy < 0 || gy >= ny || gz < 0 || gz >= nz;
-                    if (out) {
-                        const R dxg = R(gx) - R(a.xc[0]), dyg = R(gy) - R(a.xc[1]), dzg = R(gz) - R(a.xc[2]);
-                        const R ux = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
-                        const R uy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
-                        const R uz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
-                        const R usq = ux * ux + uy * uy + uz * uz;
-#pragma unroll
-                        for (int s = 0; s < 2; ++s)
-                            Prec<P>::store(dst + (int64_t)(s * Q + i) * N + idx,
-                                           equilibrium<R>(i, rhob[s], ux, uy, uz, usq), wref[s][i]);
-                    }
+                    Prec<P>::bstore(rd[s], dvo, 0, pst, w_of<R>(i) * rref[s]);
                 }
             }
         }
-        // ---- 4. roll the register window ----
+        if (GHOST && y < ny) {
+            // Populations streaming in from ghost nodes: the ghost at x_g = x - c_i
+            // holds g_eq(rho_b, A (x_g - x_c)).
+            const double *Arow = a.atab + ((int64_t)box * a.table_len + (n - a.tab_first[box])) * 9;
+            R Am[9];  // read once: the stores below may alias the table as far as the compiler knows
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+            for (int q = 0; q < 9; ++q) Am[q] = R(__builtin_nontemporal_load(Arow + q));
+            // (a) x faces, which every row touches: the lanes of the wave share the
+            // work, lane j writing direction j/2 of the five with c_x pointing into
+            // the box, component j%2, for the row's face node.
+            const bool row_lo = (x0 == 0), row_hi = (x0 + tw == nx);
+            for (int side = 0; side < 2; ++side) {
+                if (!(side ? row_hi : row_lo) || lx >= 10) continue;
+                const int fx = side ? nx - 1 : 0;
+                const int sgn = side ? -1 : 1;  // c_x of the incoming directions
+                const int m = lx >> 1, s = lx & 1;
+                // incoming direction (sgn, cyv, czv): m = 0..4 -> (0,0), (1,0), (-1,0), (0,1), (0,-1)
+                const int cyv = m == 1 ? 1 : (m == 2 ? -1 : 0);
+                const int czv = m == 3 ? 1 : (m == 4 ? -1 : 0);
+                const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
+                                        : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
+                const R dxg = R(fx - sgn) - R(a.xc[0]), dyg = R(y - cyv) - R(a.xc[1]), dzg = R(zc - czv) - R(a.xc[2]);
+                const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
+                const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
+                const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
+                const R cu = R(sgn) * gx + R(cyv) * gy + R(czv) * gz;
+                const R usq = gx * gx + gy * gy + gz * gz;
+                const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
+                const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
+                const uint32_t fnode = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(fx);
+                Prec<P>::bstore(s ? rd[1] : rd[0], fnode * EB + uint32_t(idx) * plane_bytes, 0, geq,
+                                wgt * (s ? rref[1] : rref[0]));
+            }
+            // (b) y and z faces (whole rows and planes): each boundary lane writes
+            // the directions whose source leaves the box through y or z and that
+            // the x-face pass has not written.
+            if (valid && (ylo || yhi || zlo || zhi)) {
+                const R dx0 = R(x) - R(a.xc[0]), dy0 = R(y) - R(a.xc[1]), dz0 = R(zc) - R(a.xc[2]);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) fprev[s][i] = fcur[s][i];
-            rho_p[s] = rho_c[s];
-            j_p[s][0] = j_c[s][0];
-            j_p[s][1] = j_c[s][1];
-            j_p[s][2] = j_c[s][2];
+                for (int i = 1; i < Q; ++i) {
+                    if (cy_of(i) == 0 && cz_of(i) == 0) continue;
+                    const bool from_yz = (cy_of(i) > 0 && ylo) || (cy_of(i) < 0 && yhi) || (cz_of(i) > 0 && zlo) ||
+                                         (cz_of(i) < 0 && zhi);
+                    const bool from_x = (cx_of(i) > 0 && xlo) || (cx_of(i) < 0 && xhi);
+                    if (from_yz && !from_x) {
+                        const R dxg = dx0 - R(cx_of(i)), dyg = dy0 - R(cy_of(i)), dzg = dz0 - R(cz_of(i));
+                        const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
+                        const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
+                        const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
+                        R cu = R(0);
+                        if (cx_of(i)) cu += R(cx_of(i)) * gx;
+                        if (cy_of(i)) cu += R(cy_of(i)) * gy;
+                        if (cz_of(i)) cu += R(cz_of(i)) * gz;
+                        const R usq = gx * gx + gy * gy + gz * gz;
+                        const R br = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq;
+#pragma unroll
+                        for (int s = 0; s < 2; ++s)
+                            Prec<P>::bstore(rd[s], vo + uint32_t(i) * plane_bytes, 0, w_of<R>(i) * rhob[s] * br,
+                                            w_of<R>(i) * rref[s]);
+                    }
+                }
+            }
         }
     }
 }
