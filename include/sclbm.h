@@ -180,7 +180,7 @@ sclbm_status sclbm_state_bytes(const sclbm_ctx *ctx, size_t *bytes);
 sclbm_status sclbm_save(sclbm_ctx *ctx, void *host_buf, size_t bytes);
 sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
 
-/* Launch shape of the step kernel: rows per tile (2, 4 or 8) and planes per
+/* Launch shape of the step kernel: rows per tile (4 or 8) and planes per
  * z-chunk (>= 1).  Both only change speed, never results. */
 sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk);
 sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk);

@@ -29,6 +29,22 @@ __host__ __device__ constexpr int cz_of(int i) {
     constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
     return v[i];
 }
+// Run-time lookups of the same table (for loops that are deliberately not
+// unrolled): 2-bit codes per direction, 1 -> +1, 3 -> -1, 0 -> 0.
+__host__ __device__ constexpr uint64_t pack_codes(int axis) {
+    uint64_t p = 0;
+    for (int i = 0; i < Q; ++i) {
+        const int c = axis == 0 ? cx_of(i) : (axis == 1 ? cy_of(i) : cz_of(i));
+        p |= uint64_t(c == 0 ? 0 : (c > 0 ? 1 : 3)) << (2 * i);
+    }
+    return p;
+}
+__device__ __forceinline__ int c_rt(int axis, int i) {
+    const uint64_t p = axis == 0 ? pack_codes(0) : (axis == 1 ? pack_codes(1) : pack_codes(2));
+    const int code = int((p >> (2 * i)) & 3);
+    return code == 0 ? 0 : (code == 1 ? 1 : -1);
+}
+
 template <typename R>
 __host__ __device__ constexpr R w_of(int i) {
     return i == 0 ? R(1) / R(3) : (i < 7 ? R(1) / R(18) : R(1) / R(36));
@@ -37,9 +53,10 @@ __host__ __device__ constexpr R w_of(int i) {
 // Storage formats.  S is what lives in HBM, W the type a loaded population is
 // held in registers (exactly representable from S), R the arithmetic type.
 // FP32 storage computes in FP64: on gfx950 the FP64 vector rate equals the
-// unpacked FP32 rate, and FP32 collide arithmetic accumulates cancellation error
-// in the moments and the non-equilibrium part (about 100x the storage
-// rounding after 500 steps of the droplet box).
+// unpacked FP32 rate, and FP32 collide arithmetic drifts (the FP32-rounded
+// lattice weights do not sum to one, so every collision creates or destroys a
+// little mass; after 500 steps of the droplet box the densities are off by
+// 2e-5, about 100x the storage rounding).
 // The deviation formats hold d_i = f_i - w_i rho_ref in 16 bits with FP32
 // arithmetic; the reference density of each component is a context constant.
 // Raw buffer access (CDNA buffer instructions): a 128-bit descriptor per
@@ -48,7 +65,6 @@ __host__ __device__ constexpr R w_of(int i) {
 // layout of the gfx9 family.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-
 __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000);
 }

@@ -129,9 +129,12 @@ sclbm_status check_box(const sclbm_ctx *c, int32_t box, bool allow_all) {
     return SCLBM_OK;
 }
 
+// z-chunk so that the grid holds about two resident waves per SIMD
+// (256 CUs x 4 SIMDs x 2 waves = 2048 waves = 2048 / TY workgroups).
 int default_zchunk(const sclbm_config &c, int ty) {
     const long tiles = long((c.nx + 63) / 64) * long((c.ny + ty - 1) / ty) * c.nbox;
-    long zc = (tiles * c.nz) / 1024;  // aim at >= 1024 workgroups (4 per CU)
+    const long groups = 2048 / ty;
+    long zc = (tiles * c.nz + groups - 1) / groups;
     zc = std::max(2L, std::min(zc, long(c.nz)));
     return int(zc);
 }
@@ -153,7 +156,6 @@ hipError_t launch_step_ty(sclbm_ctx *c, const StepArgs &a) {
 template <int P>
 hipError_t launch_step(sclbm_ctx *c, const StepArgs &a) {
     switch (c->tile_rows) {
-        case 2: return launch_step_ty<P, 2>(c, a);
         case 8: return launch_step_ty<P, 8>(c, a);
         default: return launch_step_ty<P, 4>(c, a);
     }
@@ -333,8 +335,8 @@ sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t b
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->n = 0;
     c->par = 0;
-    c->tile_rows = 4;
-    c->zchunk = default_zchunk(*cfg, 4);
+    c->tile_rows = 8;
+    c->zchunk = default_zchunk(*cfg, 8);
     c->tab_first.assign(cfg->nbox, 0);
     c->tab_len.assign(cfg->nbox, 0);
     c->N = int64_t(cfg->nx) * cfg->ny * cfg->nz;
@@ -632,7 +634,7 @@ sclbm_status sclbm_load(sclbm_ctx *c, const void *host_buf, size_t bytes) {
 sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
-    if (tile_rows != 2 && tile_rows != 4 && tile_rows != 8) return fail(SCLBM_EINVAL, "tile_rows must be 2, 4 or 8");
+    if (tile_rows != 4 && tile_rows != 8) return fail(SCLBM_EINVAL, "tile_rows must be 4 or 8");
     if (zchunk < 1) return fail(SCLBM_EINVAL, "zchunk must be >= 1");
     c->tile_rows = tile_rows;
     c->zchunk = std::min<int32_t>(zchunk, c->cfg.nz);

@@ -13,11 +13,11 @@
 // row, so every population stream is a coalesced 64-wide access) and marches
 // along z through a chunk of planes.  The force at plane z needs the densities
 // of planes z-1, z, z+1 including a one-node ring around the tile; those
-// densities live in a 4-slot rolling buffer in LDS.  Per plane the workgroup
-// first sums the populations of its nodes and of the ring into densities
-// (density pass), then, one plane behind, reads its own nodes' populations a
-// second time, collides them and stores them.  Holding no populations across
-// the barrier keeps register use low enough for two waves per SIMD.  Ring
+// densities live in a 4-slot rolling buffer in LDS.  Per plane each thread
+// loads its node's 38 populations into a register window and sums them into
+// densities, the workgroup adds the ring densities, and after one barrier the
+// previous plane's window is collided and pushed.  Each population is read
+// from HBM once (the ring and chunk-end re-reads mostly hit L2).  Ring
 // densities (and the two chunk-end planes) are recomputed rather than exchanged
 // between workgroups, so a step is a single launch with no grid-wide
 // synchronisation.
@@ -84,6 +84,7 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
     using S = typename Prec<P>::S;
     using W = typename Prec<P>::W;
     using R = typename Prec<P>::R;
+    using C = R;  // collision arithmetic
     constexpr int LW = 66;  // 64 + ring
     constexpr uint32_t EB = sizeof(S);
     __shared__ R lds[4][2][TY + 2][LW];
@@ -124,63 +125,85 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
 
     const R rref[2] = {R(a.rho_ref[0]), R(a.rho_ref[1])};
     const R rhob[2] = {R(a.rho_b[0]), R(a.rho_b[1])};
+
+    static_assert(TY >= 4, "one ring node per thread needs 2 (64 + 2) + 2 TY <= 64 TY");
     const int ringN = 2 * (tw + 2) + 2 * th;
     const int nplanes = (ze - zs) + 2;
 
+    W fprev[2][Q], fcur[2][Q];
     for (int k = 0; k < nplanes; ++k) {
         const int z = zs - 1 + k;
         const int slot = k & 3;
-        // ---- 1. densities of plane z: the own node, then the ring ----
-        for (int r = tid - 64 * TY; r < ringN; r += 64 * TY) {
-            int sx, sy;
-            bool work = true;
-            if (r < 0) {
-                sx = lx + 1;
-                sy = ly + 1;
-                work = valid;
-            } else if (r < tw + 2) {
-                sx = r;
-                sy = 0;
-            } else if (r < 2 * (tw + 2)) {
-                sx = r - (tw + 2);
-                sy = th + 1;
-            } else if (r < 2 * (tw + 2) + th) {
-                sx = 0;
-                sy = r - 2 * (tw + 2) + 1;
-            } else {
-                sx = tw + 1;
-                sy = r - 2 * (tw + 2) - th + 1;
+        // ---- 1. densities of plane z: own node (into the register window) and one
+        // ring node per thread (ringN <= 64 TY for TY >= 4) ----
+        bool own_in = false, ring_on = false, ring_in = false;
+        uint32_t own_vo = 0, ring_vo = 0;
+        int rsx = 0, rsy = 0;
+        if (valid) {
+            int zz = z;
+            own_in = (z >= 0) && (z < nz);
+            if (!GHOST) {
+                zz = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+                own_in = true;
             }
-            if (!work) continue;
-            int gx = x0 - 1 + sx, gy = y0 - 1 + sy, gz = z;
-            bool inside = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+            own_vo = (uint32_t(zz) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x)) * EB;
+        }
+        if (tid < ringN) {
+            const int r = tid;
+            if (r < tw + 2) {
+                rsx = r;
+                rsy = 0;
+            } else if (r < 2 * (tw + 2)) {
+                rsx = r - (tw + 2);
+                rsy = th + 1;
+            } else if (r < 2 * (tw + 2) + th) {
+                rsx = 0;
+                rsy = r - 2 * (tw + 2) + 1;
+            } else {
+                rsx = tw + 1;
+                rsy = r - 2 * (tw + 2) - th + 1;
+            }
+            int gx = x0 - 1 + rsx, gy = y0 - 1 + rsy, gz = z;
+            ring_in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
             if (!GHOST) {
                 gx = gx < 0 ? gx + nx : (gx >= nx ? gx - nx : gx);
                 gy = gy < 0 ? gy + ny : (gy >= ny ? gy - ny : gy);
                 gz = gz < 0 ? gz + nz : (gz >= nz ? gz - nz : gz);
-                inside = true;
+                ring_in = true;
             }
-            R rr[2];
-            if (inside) {
-                const uint32_t vo = (uint32_t(gz) * nxy + uint32_t(gy) * uint32_t(nx) + uint32_t(gx)) * EB;
+            ring_on = true;
+            ring_vo = (uint32_t(gz) * nxy + uint32_t(gy) * uint32_t(nx) + uint32_t(gx)) * EB;
+        }
+        if (own_in) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    fcur[s][i] = Prec<P>::bload(rs[s], own_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rref[s]);
+        }
+        if (valid) {
+            const R r0 = own_in ? pair_density<R>(fcur[0]) : rhob[0];
+            const R r1 = own_in ? pair_density<R>(fcur[1]) : rhob[1];
+            lds[slot][0][ly + 1][lx + 1] = r0;
+            lds[slot][1][ly + 1][lx + 1] = r1;
+        }
+        if (ring_on) {
+            R rr[2] = {rhob[0], rhob[1]};
+            if (ring_in) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     W f[Q];
 #pragma unroll
                     for (int i = 0; i < Q; ++i)
-                        f[i] = Prec<P>::bload(rs[s], vo + uint32_t(i) * plane_bytes, 0, w_of<R>(i) * rref[s]);
+                        f[i] = Prec<P>::bload(rs[s], ring_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rref[s]);
                     rr[s] = pair_density<R>(f);
                 }
-            } else {
-                rr[0] = rhob[0];
-                rr[1] = rhob[1];
             }
-            lds[slot][0][sy][sx] = rr[0];
-            lds[slot][1][sy][sx] = rr[1];
+            lds[slot][0][rsy][rsx] = rr[0];
+            lds[slot][1][rsy][rsx] = rr[1];
         }
         __syncthreads();
-        if (k < 2) continue;
-
+        if (k >= 2) {
         // ---- 2. collide plane z-1 and push ----
         const int zc = z - 1;
         const uint32_t node = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
@@ -188,13 +211,7 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
         const bool xlo = x == 0, xhi = x == nx - 1, ylo = y == 0, yhi = y == ny - 1;
         const bool zlo = zc == 0, zhi = zc == nz - 1;
         if (valid) {
-            // populations of the own node (second read of this plane)
-            W f[2][Q];
-#pragma unroll
-            for (int s = 0; s < 2; ++s)
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    f[s][i] = Prec<P>::bload(rs[s], vo + uint32_t(i) * plane_bytes, 0, w_of<R>(i) * rref[s]);
+            const W (&f)[2][Q] = fprev;  // populations of plane z-1, loaded one plane ago
             // moments, Eq. 6: density and momentum from pair sums and differences
             R rho[2], j[2][3];
 #pragma unroll
@@ -233,30 +250,19 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                              (j[0][2] * om0 + j[1][2] * om1) * inv_den};
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const R om = s ? om1 : om0;
+                const C om = C(s ? om1 : om0);
                 const R gt = R(a.g) * R(a.tau[s]);
-                const R ux = up[0] - gt * sig[s][0];
-                const R uy = up[1] - gt * sig[s][1];
-                const R uz = up[2] - gt * sig[s][2];
-                const R usq = ux * ux + uy * uy + uz * uz;
-                const R r = rho[s];
-                const R aa = r - R(1.5) * r * usq;
-                const R r3 = R(3) * r, r45 = R(4.5) * r;
-                R feq[Q];
-                feq[0] = aa;
-#pragma unroll
-                for (int p = 1; p <= 9; ++p) {
-                    const int i = 2 * p - 1;
-                    R cu = R(0);
-                    if (cx_of(i)) cu += R(cx_of(i)) * ux;
-                    if (cy_of(i)) cu += R(cy_of(i)) * uy;
-                    if (cz_of(i)) cu += R(cz_of(i)) * uz;
-                    eq_pair<R>(cu, aa, r3, r45, feq[i], feq[i + 1]);
-                }
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const R fi = R(f[s][i]);
-                    const R pst = fi + om * (w_of<R>(i) * feq[i] - fi);
+                const C ux = C(up[0] - gt * sig[s][0]);
+                const C uy = C(up[1] - gt * sig[s][1]);
+                const C uz = C(up[2] - gt * sig[s][2]);
+                const C usq = ux * ux + uy * uy + uz * uz;
+                const C r = C(rho[s]);
+                const C aa = r - C(1.5) * r * usq;
+                const C r3 = C(3) * r, r45 = C(4.5) * r;
+                // rest population, then the nine opposite pairs: equilibrium, collision, push
+                auto push = [&](int i, C feq_i) {
+                    const C fi = C(f[s][i]);
+                    const C pst = fi + om * (w_of<C>(i) * feq_i - fi);
                     uint32_t dvo;
                     if (GHOST) {
                         const bool out = (cx_of(i) < 0 && xlo) || (cx_of(i) > 0 && xhi) || (cy_of(i) < 0 && ylo) ||
@@ -272,6 +278,19 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                               uint32_t(i) * plane_bytes;
                     }
                     Prec<P>::bstore(rd[s], dvo, 0, pst, w_of<R>(i) * rref[s]);
+                };
+                push(0, aa);
+#pragma unroll
+                for (int p = 1; p <= 9; ++p) {
+                    const int i = 2 * p - 1;
+                    C cu = C(0);
+                    if (cx_of(i)) cu += C(cx_of(i)) * ux;
+                    if (cy_of(i)) cu += C(cy_of(i)) * uy;
+                    if (cz_of(i)) cu += C(cz_of(i)) * uz;
+                    C fplus, fminus;
+                    eq_pair<C>(cu, aa, r3, r45, fplus, fminus);
+                    push(i, fplus);
+                    push(i + 1, fminus);
                 }
             }
         }
@@ -313,31 +332,33 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
             // the x-face pass has not written.
             if (valid && (ylo || yhi || zlo || zhi)) {
                 const R dx0 = R(x) - R(a.xc[0]), dy0 = R(y) - R(a.xc[1]), dz0 = R(zc) - R(a.xc[2]);
-#pragma unroll
+                // not unrolled: only rows and planes on a y or z face take this path
+#pragma nounroll
                 for (int i = 1; i < Q; ++i) {
-                    if (cy_of(i) == 0 && cz_of(i) == 0) continue;
-                    const bool from_yz = (cy_of(i) > 0 && ylo) || (cy_of(i) < 0 && yhi) || (cz_of(i) > 0 && zlo) ||
-                                         (cz_of(i) < 0 && zhi);
-                    const bool from_x = (cx_of(i) > 0 && xlo) || (cx_of(i) < 0 && xhi);
-                    if (from_yz && !from_x) {
-                        const R dxg = dx0 - R(cx_of(i)), dyg = dy0 - R(cy_of(i)), dzg = dz0 - R(cz_of(i));
-                        const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
-                        const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
-                        const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
-                        R cu = R(0);
-                        if (cx_of(i)) cu += R(cx_of(i)) * gx;
-                        if (cy_of(i)) cu += R(cy_of(i)) * gy;
-                        if (cz_of(i)) cu += R(cz_of(i)) * gz;
-                        const R usq = gx * gx + gy * gy + gz * gz;
-                        const R br = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq;
+                    const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
+                    const bool from_yz = (cy > 0 && ylo) || (cy < 0 && yhi) || (cz > 0 && zlo) || (cz < 0 && zhi);
+                    const bool from_x = (cx > 0 && xlo) || (cx < 0 && xhi);
+                    if (!from_yz || from_x) continue;
+                    const R dxg = dx0 - R(cx), dyg = dy0 - R(cy), dzg = dz0 - R(cz);
+                    const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
+                    const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
+                    const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
+                    const R cu = R(cx) * gx + R(cy) * gy + R(cz) * gz;
+                    const R usq = gx * gx + gy * gy + gz * gz;
+                    const R br = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq;
+                    const R wgt = i < 7 ? R(1) / R(18) : R(1) / R(36);
 #pragma unroll
-                        for (int s = 0; s < 2; ++s)
-                            Prec<P>::bstore(rd[s], vo + uint32_t(i) * plane_bytes, 0, w_of<R>(i) * rhob[s] * br,
-                                            w_of<R>(i) * rref[s]);
-                    }
+                    for (int s = 0; s < 2; ++s)
+                        Prec<P>::bstore(rd[s], vo + uint32_t(i) * plane_bytes, 0, wgt * rhob[s] * br, wgt * rref[s]);
                 }
             }
         }
+        }  // k >= 2
+        // ---- 3. roll the register window ----
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) fprev[s][i] = fcur[s][i];
     }
 }
 
