@@ -40,16 +40,21 @@ def step_kernel_source_hash() -> str:
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter runs,
-    if they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_step_%s_traffic.json" % workload)
+    """HBM bytes per step-kernel launch (FETCH_SIZE + WRITE_SIZE, each scaled by
+    the same counter's reading for a plain copy of known size) from the committed
+    rocprofv3 summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_step_%s_traffic.txt" % workload)
     if not os.path.exists(path):
         return None
+    d = {}
     with open(path) as fh:
-        d = json.load(fh)
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                d[k.strip()] = v.strip()
     if d.get("source_hash") != step_kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return int(d["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(case, seconds: float = 15.0):
@@ -158,15 +163,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": case.name, "box": case.n, "radius": case.radius, "lattice_steps_per_step": STRIDE,
                    "lattice_steps_timed": STRIDE * K, "tau": case.tau, "g_ab": wl.G_AB,
-                   "storage": "fp32 SoA, 2x19 populations", "launch": {"tile_rows": ty, "zchunk": zc},
+                   "storage": "fp32 SoA, 2x19 populations (arithmetic fp64)", "launch": {"tile_rows": ty, "zchunk": zc},
                    "ca_max": round(float(ca.max()), 4), "ca_mean": round(float(ca.mean()), 4),
                    "mass_drift_rel": [float(v) for v in ((m1 - m0) / m0)],
                    "semi_axes_last": [round(float(v), 4) for v in axes[-1]]},
-        "roofline": {"bound": "hbm", "kernel": "k_step<f32>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_step<fp32 storage>", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(case.name),
                      "bytes_per_launch": bytes_per_lup * nodes, "avg_launch_ms": round(step_ms, 5)},
     }
