@@ -79,6 +79,54 @@ def cpu_baseline(case, seconds: float = 15.0):
                       % (steps, case.n, steps, el)}
 
 
+def precision_study(sc, nsteps: int):
+    """The 256^3 droplet box (R = 32, OU drive seed 3) in every storage format:
+    MLUPS, algorithmic bytes per update, mass drift and semi-axis / deformation
+    error against the FP64 GPU run, from the droplet moments every 50 steps."""
+    import torch
+    case = wl.case_c3(prec="f64", nsteps=nsteps + 1)
+    tab = case.tables[0]
+    nodes = case.n ** 3
+    bpl = {"f64": 608, "f32": 304, "f16dev": 160, "bf16dev": 160}
+    series = {}
+    out = {"workload": "c3_256cube_ou", "box": case.n, "radius": case.radius, "lattice_steps": nsteps,
+           "results": {}}
+    for prec in ("f64", "f32", "f16dev", "bf16dev"):
+        lat = sc.Lattice(case.n, case.n, case.n, bc="ghost", prec=prec, table_len=nsteps, g_ab=wl.G_AB,
+                         rho_b=case.rho_b, mach_max=wl.MACH_MAX)
+        lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
+        lat.set_gradient_table(tab[:nsteps], 0)
+        m0, _ = lat.totals()
+        ns = nsteps // STRIDE
+        mom = torch.zeros((ns, 10), dtype=torch.float64, device=lat.device)
+        lat.synchronize()
+        t0 = time.perf_counter()
+        for k in range(ns):
+            lat.step(STRIDE)
+            lat.droplet_moments(mom[k])
+        lat.synchronize()
+        el = time.perf_counter() - t0
+        m1, _ = lat.totals(check=False)
+        mm = mom.cpu().numpy()
+        st = [sc.sclbm_droplet_from_moments(mm[i], lat.xc) for i in range(ns)]
+        series[prec] = (np.array([x["semi_axes"] for x in st]), np.array([x["deformation"] for x in st]))
+        r = {"mlups": round(nodes * STRIDE * ns / el / 1e6, 1), "bytes_per_update": bpl[prec],
+             "mass_drift_rel": [float(v) for v in (m1 - m0) / m0]}
+        if prec != "f64":
+            a64, d64 = series["f64"]
+            a, d = series[prec]
+            r["semi_axes_rel_err_max"] = float(np.max(np.abs(a - a64) / a64))
+            r["deformation_abs_err_max"] = float(np.max(np.abs(d - d64)))
+        out["results"][prec] = r
+        print(json.dumps({prec: r}), flush=True)
+        lat.close()
+        del lat, mom
+        torch.cuda.empty_cache()
+    a64, d64 = series["f64"]
+    out["f64_deformation_range"] = [float(d64.min()), float(d64.max())]
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +135,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--launch", type=str, default="", help="tile_rows,zchunk")
+    ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
+                    help="c2: the headline 128^3 FP32 box (default); c3: the 256^3 precision study")
+    ap.add_argument("--c3-steps", type=int, default=10000)
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -108,6 +159,9 @@ def main():
     import paper_2112_09972_amd as sc
     global wl
     from paper_2112_09972_amd import workloads as wl
+    if args.workload == "c3":
+        precision_study(sc, args.c3_steps)
+        return
 
     K, W = args.steps, args.warmup
     total_steps = (K + W) * STRIDE

@@ -40,9 +40,8 @@ struct DropletInit {
 
 // mode 0: tanh droplet (DropletInit); mode 1: FP64 fields rho_a, rho_b, u.
 template <int P>
-__global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, BoxGeom g, int mode, DropletInit d,
-                                              const double *rho_a, const double *rho_b, const double *u,
-                                              double rref0, double rref1) {
+__global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, __half *ref, BoxGeom g, int mode, DropletInit d,
+                                              const double *rho_a, const double *rho_b, const double *u) {
     using R = typename Prec<P>::R;
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= g.nnode) return;
@@ -73,26 +72,32 @@ __global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, BoxGeom g,
     }
     const double usq = ux * ux + uy * uy + uz * uz;
     const double rr[2] = {ra, rb};
-    const double rref[2] = {rref0, rref1};
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < 2; ++s) {
+        double rref = 0.0;
+        if (Prec<P>::DEV) {
+            ref_store(ref + s * g.nnode + k, float(rr[s]));
+            rref = ref_load(ref + s * g.nnode + k);
+        }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const double fe = equilibrium<double>(i, rr[s], ux, uy, uz, usq);
-            Prec<P>::store(f + (int64_t)(s * Q + i) * g.nnode + k, R(fe), R(w_of<double>(i) * rref[s]));
+            Prec<P>::store(f + (int64_t)(s * Q + i) * g.nnode + k, R(fe), R(w_of<R>(i) * R(rref)));
         }
+    }
 }
 
 template <int P>
-__device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, int64_t N, int64_t k, const double rref[2],
+__device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, const __half *ref, int64_t N, int64_t k,
                                              double rho[2], double j[2][3]) {
     using R = typename Prec<P>::R;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         R r = R(0), jx = R(0), jy = R(0), jz = R(0);
+        const R rref = Prec<P>::DEV ? R(ref_load(ref + s * N + k)) : R(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R v = R(Prec<P>::load(f + (int64_t)(s * Q + i) * N + k, R(w_of<double>(i) * rref[s])));
+            const R v = R(Prec<P>::load(f + (int64_t)(s * Q + i) * N + k, w_of<R>(i) * rref));
             r += v;
             if (cx_of(i)) jx += R(cx_of(i)) * v;
             if (cy_of(i)) jy += R(cy_of(i)) * v;
@@ -106,13 +111,12 @@ __device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, int64
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_density(const typename Prec<P>::S *f, BoxGeom g, double rref0, double rref1,
+__global__ __launch_bounds__(256) void k_density(const typename Prec<P>::S *f, const __half *ref, BoxGeom g,
                                                  double *rho_a, double *rho_b) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= g.nnode) return;
-    const double rref[2] = {rref0, rref1};
     double rho[2], j[2][3];
-    node_moments<P>(f, g.nnode, k, rref, rho, j);
+    node_moments<P>(f, ref, g.nnode, k, rho, j);
     rho_a[k] = rho[0];
     rho_b[k] = rho[1];
 }
@@ -120,14 +124,13 @@ __global__ __launch_bounds__(256) void k_density(const typename Prec<P>::S *f, B
 // Barycentric velocity with the half-force term; force from the FP64 density
 // arrays written by k_density (same neighbour rules as the step kernel).
 template <int P>
-__global__ __launch_bounds__(256) void k_velocity(const typename Prec<P>::S *f, BoxGeom g, double rref0, double rref1,
+__global__ __launch_bounds__(256) void k_velocity(const typename Prec<P>::S *f, const __half *ref, BoxGeom g,
                                                   const double *rho_a, const double *rho_b, int ghost, double gab,
                                                   double rb0, double rb1, double *u) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= g.nnode) return;
-    const double rref[2] = {rref0, rref1};
     double rho[2], j[2][3];
-    node_moments<P>(f, g.nnode, k, rref, rho, j);
+    node_moments<P>(f, ref, g.nnode, k, rho, j);
     int x, y, z;
     node_xyz(g, k, x, y, z);
     const double *rf[2] = {rho_a, rho_b};
@@ -189,16 +192,15 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[K], double *out /
 // Per-workgroup partials of: mass A, mass B, momentum (3), indicator moments
 // S0, S1 (3), S2 (6) about the box centre, and the count of bad nodes.
 template <int P>
-__global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::S *f, BoxGeom g, double rref0,
-                                                        double rref1, double *partial) {
+__global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::S *f, const __half *ref, BoxGeom g,
+                                                        double *partial) {
     double v[NSTAT];
 #pragma unroll
     for (int c = 0; c < NSTAT; ++c) v[c] = 0.0;
-    const double rref[2] = {rref0, rref1};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.nnode; k += stride) {
         double rho[2], j[2][3];
-        node_moments<P>(f, g.nnode, k, rref, rho, j);
+        node_moments<P>(f, ref, g.nnode, k, rho, j);
         v[0] += rho[0];
         v[1] += rho[1];
         v[2] += j[0][0] + j[1][0];

@@ -57,8 +57,12 @@ __host__ __device__ constexpr R w_of(int i) {
 // lattice weights do not sum to one, so every collision creates or destroys a
 // little mass; after 500 steps of the droplet box the densities are off by
 // 2e-5, about 100x the storage rounding).
-// The deviation formats hold d_i = f_i - w_i rho_ref in 16 bits with FP32
-// arithmetic; the reference density of each component is a context constant.
+// The deviation formats hold d_i = f_i / (w_i rho_ref(x)) - 1 in 16 bits with FP32
+// arithmetic, rho_ref(x) being the node's own density one step earlier, kept
+// per node and component in FP16 (DEV = true).  A constant reference fails in
+// a two-phase box: the minority component inside the other phase deviates from
+// w_i rho_ref by as much as the population itself (2.8e-2 density error after
+// 500 steps of the 32^3 droplet box in FP16, 0.31 in BF16).
 // Raw buffer access (CDNA buffer instructions): a 128-bit descriptor per
 // population array in SGPRs, a uniform byte offset per direction (SGPR) and one
 // 32-bit byte offset per lane.  Word 3 = 0x00020000 is the raw 32-bit-element
@@ -69,10 +73,18 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes), 0x00020000);
 }
 
+// Relative deviation (v - wref) / wref that the 16-bit formats store: it keeps
+// the formats' relative precision at every size of deviation (an absolute
+// deviation below 6e-5 would fall into FP16's subnormal range, whose spacing of
+// 6e-8 is 1e-5 of a minority-phase population).  The reader rebuilds
+// wref (1 + d); any consistent reciprocal will do.
+__device__ __forceinline__ float rel_dev(float v, float wref) { return (v - wref) * __builtin_amdgcn_rcpf(wref); }
+
 template <int P>
 struct Prec;
 template <>
 struct Prec<SCLBM_F64> {
+    static constexpr bool DEV = false;
     using S = double;
     using W = double;
     using R = double;
@@ -87,6 +99,7 @@ struct Prec<SCLBM_F64> {
 };
 template <>
 struct Prec<SCLBM_F32> {
+    static constexpr bool DEV = false;
     using S = float;
     using W = float;
     using R = double;
@@ -101,36 +114,46 @@ struct Prec<SCLBM_F32> {
 };
 template <>
 struct Prec<SCLBM_F16DEV> {
+    static constexpr bool DEV = true;
     using S = __half;
     using W = float;
     using R = float;
-    static __device__ __forceinline__ W load(const S *p, R wref) { return wref + __half2float(*p); }
-    static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2half_rn(v - wref); }
+    static __device__ __forceinline__ W load(const S *p, R wref) { return wref + wref * __half2float(*p); }
+    static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2half_rn(rel_dev(v, wref)); }
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-        return wref + __half2float(__builtin_bit_cast(__half, b));
+        return wref + wref * __half2float(__builtin_bit_cast(__half, b));
     }
     static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(v - wref)), r, vo,
-                                              so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(rel_dev(v, wref))), r,
+                                              vo, so, 0);
     }
 };
 template <>
 struct Prec<SCLBM_BF16DEV> {
+    static constexpr bool DEV = true;
     using S = __hip_bfloat16;
     using W = float;
     using R = float;
-    static __device__ __forceinline__ W load(const S *p, R wref) { return wref + __bfloat162float(*p); }
-    static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2bfloat16(v - wref); }
+    static __device__ __forceinline__ W load(const S *p, R wref) { return wref + wref * __bfloat162float(*p); }
+    static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2bfloat16(rel_dev(v, wref)); }
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-        return wref + __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
+        return wref + wref * __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
     }
     static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(v - wref)), r, vo,
-                                              so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(rel_dev(v, wref))), r,
+                                              vo, so, 0);
     }
 };
+
+// Per-node reference densities of the deviation formats (FP16; only their
+// consistency between writer and reader matters, not their precision).
+__device__ __forceinline__ float ref_load(const __half *p) { return __half2float(*p); }
+__device__ __forceinline__ float ref_round(float v) { return __half2float(__float2half_rn(v)); }
+__device__ __forceinline__ void ref_store(__half *p, float v) { *p = __float2half_rn(v); }
+
+inline bool is_dev(int prec) { return prec == SCLBM_F16DEV || prec == SCLBM_BF16DEV; }
 
 inline size_t elem_bytes(int prec) {
     switch (prec) {

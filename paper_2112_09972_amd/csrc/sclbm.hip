@@ -49,8 +49,9 @@ constexpr size_t kAlign = 256;
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t f0, f1, atab, first, clock, partial, result, diag, total;
-    size_t fbytes;
+    size_t f0, f1, ref0, ref1, atab, first, clock, partial, result, diag, total;
+    size_t fbytes;    // populations of every box, one buffer
+    size_t refbytes;  // per-node FP16 reference densities (deviation formats), one buffer
 };
 
 bool config_ok(const sclbm_config *c, std::string &why) {
@@ -80,9 +81,12 @@ Layout make_layout(const sclbm_config *c) {
     Layout L{};
     const size_t N = size_t(c->nx) * c->ny * c->nz;
     L.fbytes = size_t(c->nbox) * 2 * Q * N * elem_bytes(c->prec);
+    L.refbytes = is_dev(c->prec) ? size_t(c->nbox) * 2 * N * 2 : 0;
     size_t off = 0;
     L.f0 = off; off += round_up(L.fbytes);
     L.f1 = off; off += round_up(L.fbytes);
+    L.ref0 = off; off += round_up(L.refbytes);
+    L.ref1 = off; off += round_up(L.refbytes);
     L.atab = off; off += round_up(size_t(c->nbox) * size_t(c->bc == SCLBM_BC_GHOST ? c->table_len : 0) * 9 * 8);
     L.first = off; off += round_up(size_t(c->nbox) * 8);
     L.clock = off; off += round_up(2 * 8);
@@ -109,6 +113,10 @@ struct sclbm_ctx {
     BoxGeom geom;
 
     void *fbuf(int which) { return ws + (which ? lay.f1 : lay.f0); }
+    __half *refbuf(int which) {
+        return lay.refbytes ? reinterpret_cast<__half *>(ws + (which ? lay.ref1 : lay.ref0)) : nullptr;
+    }
+    __half *box_ref(int which, int box) { return lay.refbytes ? refbuf(which) + size_t(box) * 2 * size_t(N) : nullptr; }
     size_t box_bytes() const { return size_t(2) * Q * size_t(N) * elem_bytes(cfg.prec); }
     double *partial() { return reinterpret_cast<double *>(ws + lay.partial); }
     double *result() { return reinterpret_cast<double *>(ws + lay.result); }
@@ -192,8 +200,8 @@ sclbm_status init_common(sclbm_ctx *c, int32_t box, int mode, const DropletInit 
             constexpr int P = decltype(pc)::value;
             using S = typename Prec<P>::S;
             S *f = reinterpret_cast<S *>(c->fbuf(c->par)) + size_t(b) * 2 * Q * size_t(c->N);
-            hipLaunchKernelGGL((k_init<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f, c->geom, mode, d, ra,
-                               rb, u, c->cfg.rho_b[0], c->cfg.rho_b[1]);
+            hipLaunchKernelGGL((k_init<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f, c->box_ref(c->par, b),
+                               c->geom, mode, d, ra, rb, u);
             return hipGetLastError();
         });
         if (e != hipSuccess) return fail(SCLBM_EHIP, "init kernel: %s", hipGetErrorString(e));
@@ -274,8 +282,8 @@ sclbm_status launch_stats(sclbm_ctx *c, int32_t box) {
         constexpr int P = decltype(pc)::value;
         using S = typename Prec<P>::S;
         const S *f = reinterpret_cast<const S *>(c->fbuf(c->par)) + size_t(box) * 2 * Q * size_t(c->N);
-        hipLaunchKernelGGL((k_stats<P>), dim3(NRED_BLOCKS), dim3(NRED_THREADS), 0, c->stream, f, c->geom,
-                           c->cfg.rho_b[0], c->cfg.rho_b[1], c->partial());
+        hipLaunchKernelGGL((k_stats<P>), dim3(NRED_BLOCKS), dim3(NRED_THREADS), 0, c->stream, f,
+                           c->box_ref(c->par, box), c->geom, c->partial());
         return hipGetLastError();
     });
     if (e != hipSuccess) return fail(SCLBM_EHIP, "stats kernel: %s", hipGetErrorString(e));
@@ -290,12 +298,12 @@ sclbm_status fields_into(sclbm_ctx *c, int32_t box, double *ra, double *rb, doub
         constexpr int P = decltype(pc)::value;
         using S = typename Prec<P>::S;
         const S *f = reinterpret_cast<const S *>(c->fbuf(c->par)) + size_t(box) * 2 * Q * size_t(c->N);
-        hipLaunchKernelGGL((k_density<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f, c->geom,
-                           c->cfg.rho_b[0], c->cfg.rho_b[1], ra, rb);
+        hipLaunchKernelGGL((k_density<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f,
+                           c->box_ref(c->par, box), c->geom, ra, rb);
         hipError_t e1 = hipGetLastError();
         if (e1 != hipSuccess || !u) return e1;
-        hipLaunchKernelGGL((k_velocity<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f, c->geom,
-                           c->cfg.rho_b[0], c->cfg.rho_b[1], ra, rb, int(c->cfg.bc == SCLBM_BC_GHOST), c->cfg.g_ab,
+        hipLaunchKernelGGL((k_velocity<P>), dim3(grid1d(c->N, 256)), dim3(256), 0, c->stream, f,
+                           c->box_ref(c->par, box), c->geom, ra, rb, int(c->cfg.bc == SCLBM_BC_GHOST), c->cfg.g_ab,
                            c->cfg.rho_b[0], c->cfg.rho_b[1], u);
         return hipGetLastError();
     });
@@ -447,13 +455,14 @@ sclbm_status sclbm_step(sclbm_ctx *c, int64_t nsteps) {
         a.tau[s] = c->cfg.tau[s];
         a.omega[s] = 1.0 / c->cfg.tau[s];
         a.rho_b[s] = c->cfg.rho_b[s];
-        a.rho_ref[s] = c->cfg.rho_b[s];
     }
     a.g = c->cfg.g_ab;
     for (int k = 0; k < 3; ++k) a.xc[k] = c->geom.xc[k];
     for (int64_t t = 0; t < nsteps; ++t) {
         a.src = c->fbuf(c->par);
         a.dst = c->fbuf(1 - c->par);
+        a.ref_src = c->refbuf(c->par);
+        a.ref_dst = c->refbuf(1 - c->par);
         a.clk_in = c->clock() + c->par;
         a.clk_out = c->clock() + (1 - c->par);
         hipError_t e = launch_step_prec(c, a);
@@ -572,7 +581,7 @@ sclbm_status sclbm_state_bytes(const sclbm_ctx *c, size_t *bytes) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
     if (!bytes) return fail(SCLBM_EINVAL, "null bytes pointer");
-    *bytes = 64 + c->lay.fbytes;
+    *bytes = 64 + c->lay.fbytes + c->lay.refbytes;
     return SCLBM_OK;
 }
 
@@ -590,7 +599,8 @@ sclbm_status sclbm_save(sclbm_ctx *c, void *host_buf, size_t bytes) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
     if (!host_buf) return fail(SCLBM_EINVAL, "null buffer");
-    if (bytes < 64 + c->lay.fbytes) return fail(SCLBM_ESIZE, "buffer %zu < %zu", bytes, 64 + c->lay.fbytes);
+    const size_t need = 64 + c->lay.fbytes + c->lay.refbytes;
+    if (bytes < need) return fail(SCLBM_ESIZE, "buffer %zu < %zu", bytes, need);
     CkptHeader h{};
     std::memcpy(h.magic, "SCLBMCK1", 8);
     h.n = c->n;
@@ -605,6 +615,9 @@ sclbm_status sclbm_save(sclbm_ctx *c, void *host_buf, size_t bytes) {
     std::memcpy(host_buf, &h, sizeof h);
     HIP_TRY(hipMemcpyAsync(static_cast<char *>(host_buf) + 64, c->fbuf(c->par), c->lay.fbytes, hipMemcpyDeviceToHost,
                            c->stream));
+    if (c->lay.refbytes)
+        HIP_TRY(hipMemcpyAsync(static_cast<char *>(host_buf) + 64 + c->lay.fbytes, c->refbuf(c->par), c->lay.refbytes,
+                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return SCLBM_OK;
 }
@@ -620,9 +633,12 @@ sclbm_status sclbm_load(sclbm_ctx *c, const void *host_buf, size_t bytes) {
     if (h.nx != c->cfg.nx || h.ny != c->cfg.ny || h.nz != c->cfg.nz || h.nbox != c->cfg.nbox ||
         h.prec != c->cfg.prec || h.bc != c->cfg.bc || h.fbytes != int64_t(c->lay.fbytes))
         return fail(SCLBM_EINVAL, "checkpoint was written for a different configuration");
-    if (bytes < 64 + c->lay.fbytes) return fail(SCLBM_ESIZE, "buffer truncated");
+    if (bytes < 64 + c->lay.fbytes + c->lay.refbytes) return fail(SCLBM_ESIZE, "buffer truncated");
     HIP_TRY(hipMemcpyAsync(c->fbuf(0), static_cast<const char *>(host_buf) + 64, c->lay.fbytes, hipMemcpyHostToDevice,
                            c->stream));
+    if (c->lay.refbytes)
+        HIP_TRY(hipMemcpyAsync(c->refbuf(0), static_cast<const char *>(host_buf) + 64 + c->lay.fbytes, c->lay.refbytes,
+                               hipMemcpyHostToDevice, c->stream));
     int64_t clk[2] = {h.n, h.n};
     HIP_TRY(hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

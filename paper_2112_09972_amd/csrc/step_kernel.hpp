@@ -50,7 +50,8 @@ struct StepArgs {
     double tau[2];
     double g;                 // G_AB
     double rho_b[2];          // ghost densities
-    double rho_ref[2];        // reference densities of the deviation formats
+    const __half *ref_src;    // deviation formats: per-node reference densities of f(n) [box][2][N]
+    __half *ref_dst;          // and of f(n+1); unused otherwise
     double xc[3];             // box centre
 };
 
@@ -123,7 +124,9 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
     const int64_t n = *a.clk_in;
     if (lin == 0 && tid == 0) *a.clk_out = n + 1;
 
-    const R rref[2] = {R(a.rho_ref[0]), R(a.rho_ref[1])};
+    constexpr bool DEV = Prec<P>::DEV;
+    const __half *ref_in = DEV ? a.ref_src + (int64_t)box * 2 * N : nullptr;
+    __half *ref_out = DEV ? a.ref_dst + (int64_t)box * 2 * N : nullptr;
     const R rhob[2] = {R(a.rho_b[0]), R(a.rho_b[1])};
 
     static_assert(TY >= 4, "one ring node per thread needs 2 (64 + 2) + 2 TY <= 64 TY");
@@ -176,10 +179,12 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
         }
         if (own_in) {
 #pragma unroll
-            for (int s = 0; s < 2; ++s)
+            for (int s = 0; s < 2; ++s) {
+                const R rr = DEV ? R(ref_load(ref_in + s * N + own_vo / EB)) : R(0);
 #pragma unroll
                 for (int i = 0; i < Q; ++i)
-                    fcur[s][i] = Prec<P>::bload(rs[s], own_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rref[s]);
+                    fcur[s][i] = Prec<P>::bload(rs[s], own_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rr);
+            }
         }
         if (valid) {
             const R r0 = own_in ? pair_density<R>(fcur[0]) : rhob[0];
@@ -192,10 +197,11 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
             if (ring_in) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
+                    const R ref = DEV ? R(ref_load(ref_in + s * N + ring_vo / EB)) : R(0);
                     W f[Q];
 #pragma unroll
                     for (int i = 0; i < Q; ++i)
-                        f[i] = Prec<P>::bload(rs[s], ring_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rref[s]);
+                        f[i] = Prec<P>::bload(rs[s], ring_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * ref);
                     rr[s] = pair_density<R>(f);
                 }
             }
@@ -259,10 +265,20 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                 const C r = C(rho[s]);
                 const C aa = r - C(1.5) * r * usq;
                 const C r3 = C(3) * r, r45 = C(4.5) * r;
-                // rest population, then the nine opposite pairs: equilibrium, collision, push
+                // the nine opposite pairs, then the rest population: equilibrium, collision, push
+                // In FP32 arithmetic the rounded weights sum to 1 + 3e-8, so the single-rate
+                // update would create that much mass per collision; there the rest
+                // population takes the mass balance rho - sum_{i>0} p_i instead (equal in
+                // exact arithmetic).
+                constexpr bool BALANCE = sizeof(C) == 4;
+                C psum = C(0);
                 auto push = [&](int i, C feq_i) {
                     const C fi = C(f[s][i]);
-                    const C pst = fi + om * (w_of<C>(i) * feq_i - fi);
+                    C pst = fi + om * (w_of<C>(i) * feq_i - fi);
+                    if (BALANCE) {
+                        if (i == 0) pst = C(rho[s]) - psum;
+                        else psum += pst;
+                    }
                     uint32_t dvo;
                     if (GHOST) {
                         const bool out = (cx_of(i) < 0 && xlo) || (cx_of(i) > 0 && xhi) || (cy_of(i) < 0 && ylo) ||
@@ -277,9 +293,13 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                         dvo = (uint32_t(dz) * nxy + uint32_t(dy) * uint32_t(nx) + uint32_t(dx)) * EB +
                               uint32_t(i) * plane_bytes;
                     }
-                    Prec<P>::bstore(rd[s], dvo, 0, pst, w_of<R>(i) * rref[s]);
+                    // deviation formats: relative to the destination's density at time n,
+                    // rounded as the destination's own thread stores it below
+                    const C dref = DEV ? C(ref_round(float(lds[(k - 1 + cz_of(i)) & 3][s][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)])))
+                                       : C(0);
+                    Prec<P>::bstore(rd[s], dvo, 0, pst, w_of<C>(i) * dref);
                 };
-                push(0, aa);
+                if (DEV) ref_store(ref_out + s * N + node, float(rho[s]));
 #pragma unroll
                 for (int p = 1; p <= 9; ++p) {
                     const int i = 2 * p - 1;
@@ -292,6 +312,7 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                     push(i, fplus);
                     push(i + 1, fminus);
                 }
+                push(0, aa);
             }
         }
         if (GHOST && y < ny) {
@@ -324,8 +345,8 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                 const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
                 const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
                 const uint32_t fnode = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(fx);
-                Prec<P>::bstore(s ? rd[1] : rd[0], fnode * EB + uint32_t(idx) * plane_bytes, 0, geq,
-                                wgt * (s ? rref[1] : rref[0]));
+                const R fref = DEV ? R(ref_round(float(lds[(k - 1) & 3][s][ly + 1][fx - x0 + 1]))) : R(0);
+                Prec<P>::bstore(s ? rd[1] : rd[0], fnode * EB + uint32_t(idx) * plane_bytes, 0, geq, wgt * fref);
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
             // the directions whose source leaves the box through y or z and that
@@ -348,8 +369,10 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                     const R br = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq;
                     const R wgt = i < 7 ? R(1) / R(18) : R(1) / R(36);
 #pragma unroll
-                    for (int s = 0; s < 2; ++s)
-                        Prec<P>::bstore(rd[s], vo + uint32_t(i) * plane_bytes, 0, wgt * rhob[s] * br, wgt * rref[s]);
+                    for (int s = 0; s < 2; ++s) {
+                        const R oref = DEV ? R(ref_round(float(lds[(k - 1) & 3][s][ly + 1][lx + 1]))) : R(0);
+                        Prec<P>::bstore(rd[s], vo + uint32_t(i) * plane_bytes, 0, wgt * rhob[s] * br, wgt * oref);
+                    }
                 }
             }
         }

@@ -181,3 +181,59 @@ def test_full_size_128_fp32_all_nodes(sc):
     lat.step(steps)
     o.run(steps, tab[:steps])
     assert rel_density_error(lat, o) <= TOL["f32"]
+
+
+# Deviation formats (FP16 / BF16 storage of f_i - w_i rho_ref(x), rho_ref the
+# node's density one step earlier, FP32 arithmetic).  Tolerance derived from the
+# storage rounding: deviations are at most ~0.1 w_i rho, stored with a relative
+# half-ulp of 2^-12 (FP16) or 2^-9 (BF16), i.e. ~2.4e-5 / 2e-4 of a population per
+# step; over 500 steps a random walk gives ~5e-4 / 4e-3.  The bound is 4x that.
+DEV_TOL = {"f16dev": 2e-3, "bf16dev": 2e-2}
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_c1_deviation_formats_500_steps(sc, prec):
+    case = wl.case_c1()
+    A = case.tables[0][0]
+    steps = 500
+    lat, o = make_pair(sc, 32, prec=prec, R=case.radius, A=A, steps=steps, mach_max=0.25)
+    ref64, _ = make_pair(sc, 32, prec="f64", R=case.radius, A=A, steps=steps, mach_max=0.25)
+    tab = case.tables[0][:steps]
+    for l in (lat, ref64):
+        l.set_gradient_table(tab, 0)
+    m0, _ = lat.totals()
+    m064, _ = ref64.totals()
+    lat.step(steps)
+    ref64.step(steps)
+    o.run(steps, tab)
+    err = rel_density_error(lat, o)
+    print("%s: max rel density error %.3e" % (prec, err))
+    assert err <= DEV_TOL[prec]
+    # mass drift (the open boundary is not conservative) matches the FP64 run's
+    m, _ = lat.totals()
+    m64, _ = ref64.totals()
+    assert np.all(np.abs((m - m0) / m0 - (m64 - m064) / m064) <= DEV_TOL[prec])
+    a = lat.droplet()["semi_axes"]
+    a64 = ref64.droplet()["semi_axes"]
+    assert np.all(np.abs(a - a64) / a64 <= 2 * DEV_TOL[prec])
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_deviation_formats_stationary_and_checkpoint(sc, prec):
+    n = 20
+    rho_b = wl.ghost_densities(6.0)
+    lat = sc.Lattice(n, n, n, bc="periodic", prec=prec, g_ab=wl.G_AB, rho_b=rho_b)
+    lat.init_fields(np.full(lat.shape, rho_b[0]), np.full(lat.shape, rho_b[1]))
+    lat.step(100)
+    # at rest and uniform every deviation is zero up to FP32 rounding of w_i rho
+    ra, rb, u = (t.cpu().numpy() for t in lat.fields())
+    assert np.abs(ra / rho_b[0] - 1).max() <= 1e-6 and np.abs(rb / rho_b[1] - 1).max() <= 1e-6
+    assert np.abs(u).max() <= 1e-7
+    lat2, _ = make_pair(sc, 24, prec=prec, bc="periodic", R=6.0)
+    lat2.step(30)
+    ck = lat2.save()
+    lat2.step(30)
+    end = lat2.save()
+    lat2.load(ck)
+    lat2.step(30)
+    assert np.array_equal(lat2.save(), end)
