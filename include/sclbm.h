@@ -138,6 +138,14 @@ sclbm_status sclbm_set_gradient_table(sclbm_ctx *ctx, int32_t box, const double 
  * else ESTATE and nothing is launched. */
 sclbm_status sclbm_step(sclbm_ctx *ctx, int64_t nsteps);
 
+/* Advance every box by nsteps through a captured hipGraph of nsteps fused
+ * launches (nsteps even and >= 2).  The graph is captured on first use for this
+ * nsteps, launch shape and buffer parity, then replayed; the kernels read the
+ * time from a device counter, so a replay continues where the last one ended.
+ * Same table rules as sclbm_step.  The graph is rebuilt after sclbm_set_launch
+ * or when an odd number of eager steps changed the buffer parity. */
+sclbm_status sclbm_step_graph(sclbm_ctx *ctx, int64_t nsteps);
+
 /* Current time n. */
 sclbm_status sclbm_get_step(const sclbm_ctx *ctx, int64_t *step);
 
@@ -184,6 +192,15 @@ sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
  * z-chunk (>= 1).  Both only change speed, never results. */
 sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk);
 sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk);
+
+/* Autotuner: time trial_steps steps (after one warm-up step) for every tile
+ * height (4, 8) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz), keep the
+ * fastest and set it.  best_ms (may be NULL) receives the best average step
+ * time.  The trials overwrite the populations (call it before an init call, or
+ * re-initialise after) but restore the time.  In ghost mode every box's table
+ * must cover steps n .. n + trial_steps.  Synchronises. */
+sclbm_status sclbm_autotune(sclbm_ctx *ctx, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk,
+                            float *best_ms);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *sclbm_last_error(void);

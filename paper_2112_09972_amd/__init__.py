@@ -52,7 +52,7 @@ EXPORTS = [
     "sclbm_set_gradient_table", "sclbm_step", "sclbm_get_step", "sclbm_fields", "sclbm_totals",
     "sclbm_droplet_moments", "sclbm_droplet_from_moments", "sclbm_droplet", "sclbm_velocity_error",
     "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch",
-    "sclbm_last_error",
+    "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune",
 ]
 
 
@@ -73,6 +73,8 @@ def _load_library():
         "sclbm_init_fields": [P, I32, P, P, P],
         "sclbm_set_gradient_table": [P, I32, dp, I64, I64],
         "sclbm_step": [P, I64],
+        "sclbm_step_graph": [P, I64],
+        "sclbm_autotune": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float)],
         "sclbm_get_step": [P, ctypes.POINTER(I64)],
         "sclbm_fields": [P, I32, P, P, P],
         "sclbm_totals": [P, I32, dp, dp],
@@ -162,6 +164,18 @@ def sclbm_set_gradient_table(ctx, box, A_rows: np.ndarray, first_step: int):
 
 def sclbm_step(ctx, nsteps: int):
     _check(_lib.sclbm_step(ctx, int(nsteps)))
+
+
+def sclbm_step_graph(ctx, nsteps: int):
+    _check(_lib.sclbm_step_graph(ctx, int(nsteps)))
+
+
+def sclbm_autotune(ctx, trial_steps: int):
+    t = ctypes.c_int32()
+    z = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _check(_lib.sclbm_autotune(ctx, int(trial_steps), ctypes.byref(t), ctypes.byref(z), ctypes.byref(ms)))
+    return t.value, z.value, ms.value
 
 
 def sclbm_get_step(ctx) -> int:
@@ -306,6 +320,40 @@ class Lattice:
 
     def step(self, nsteps):
         sclbm_step(self.ctx, nsteps)
+
+    def step_graph(self, nsteps):
+        """nsteps (even) fused launches replayed from a captured hipGraph."""
+        sclbm_step_graph(self.ctx, nsteps)
+
+    def autotune(self, trial_steps=20, cache=True):
+        """Pick the fastest launch shape (clobbers the populations: call before
+        an init).  Results are cached in $XDG_CACHE_HOME/sclbm/tuning.json keyed
+        by device, box shape, boxes, precision and boundary mode."""
+        import json
+        key = "%s|%dx%dx%d|%d|%d|%d" % (self.torch.cuda.get_device_properties(self.device).name, self.nx, self.ny,
+                                        self.nz, self.nbox, self.cfg.prec, self.cfg.bc)
+        path = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "sclbm", "tuning.json")
+        table = {}
+        if cache and os.path.exists(path):
+            try:
+                with open(path) as fh:
+                    table = json.load(fh)
+            except (OSError, ValueError):
+                table = {}
+        if key in table:
+            ty, zc = table[key]["tile_rows"], table[key]["zchunk"]
+            self.set_launch(ty, zc)
+            return ty, zc, table[key]["ms"]
+        ty, zc, ms = sclbm_autotune(self.ctx, trial_steps)
+        if cache:
+            table[key] = {"tile_rows": ty, "zchunk": zc, "ms": ms}
+            try:
+                os.makedirs(os.path.dirname(path), exist_ok=True)
+                with open(path, "w") as fh:
+                    json.dump(table, fh, indent=1)
+            except OSError:
+                pass
+        return ty, zc, ms
 
     def synchronize(self):
         self.stream.synchronize()

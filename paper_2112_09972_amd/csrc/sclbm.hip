@@ -109,6 +109,10 @@ struct sclbm_ctx {
     int tile_rows;    // TY
     int zchunk;
     std::vector<int64_t> tab_first, tab_len;  // host copies, per box
+    // captured step loop: valid for (graph_steps, graph_par, graph_ty, graph_zc)
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t graph_steps = 0;
+    int graph_par = -1, graph_ty = 0, graph_zc = 0;
     int64_t N;
     BoxGeom geom;
 
@@ -125,6 +129,8 @@ struct sclbm_ctx {
 };
 
 namespace {
+
+void drop_graph(sclbm_ctx *c);
 
 sclbm_status check_ctx(const sclbm_ctx *c) {
     if (!c) return fail(SCLBM_EINVAL, "null context");
@@ -207,6 +213,7 @@ sclbm_status init_common(sclbm_ctx *c, int32_t box, int mode, const DropletInit 
         if (e != hipSuccess) return fail(SCLBM_EHIP, "init kernel: %s", hipGetErrorString(e));
     }
     c->n = 0;
+    drop_graph(c);
     int64_t zero[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(c->clock(), zero, sizeof zero, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));  // `zero` is a stack buffer
@@ -368,6 +375,7 @@ sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t b
 }
 
 sclbm_status sclbm_destroy(sclbm_ctx *ctx) {
+    if (ctx) drop_graph(ctx);
     delete ctx;
     return SCLBM_OK;
 }
@@ -429,18 +437,19 @@ sclbm_status sclbm_set_gradient_table(sclbm_ctx *c, int32_t box, const double *A
     return SCLBM_OK;
 }
 
-sclbm_status sclbm_step(sclbm_ctx *c, int64_t nsteps) {
-    sclbm_status st = check_ctx(c);
-    if (st) return st;
-    if (nsteps < 0) return fail(SCLBM_EINVAL, "nsteps < 0");
-    if (nsteps == 0) return SCLBM_OK;
-    const bool ghost = c->cfg.bc == SCLBM_BC_GHOST;
-    if (ghost)
-        for (int b = 0; b < c->cfg.nbox; ++b)
-            if (c->n < c->tab_first[b] || c->n + nsteps > c->tab_first[b] + c->tab_len[b])
-                return fail(SCLBM_ESTATE, "box %d: gradient table covers steps [%lld, %lld), need [%lld, %lld)", b,
-                            (long long)c->tab_first[b], (long long)(c->tab_first[b] + c->tab_len[b]),
-                            (long long)c->n, (long long)(c->n + nsteps));
+namespace {
+
+sclbm_status check_table(sclbm_ctx *c, int64_t nsteps) {
+    if (c->cfg.bc != SCLBM_BC_GHOST) return SCLBM_OK;
+    for (int b = 0; b < c->cfg.nbox; ++b)
+        if (c->n < c->tab_first[b] || c->n + nsteps > c->tab_first[b] + c->tab_len[b])
+            return fail(SCLBM_ESTATE, "box %d: gradient table covers steps [%lld, %lld), need [%lld, %lld)", b,
+                        (long long)c->tab_first[b], (long long)(c->tab_first[b] + c->tab_len[b]), (long long)c->n,
+                        (long long)(c->n + nsteps));
+    return SCLBM_OK;
+}
+
+StepArgs base_args(sclbm_ctx *c) {
     StepArgs a{};
     a.atab = reinterpret_cast<const double *>(c->ws + c->lay.atab);
     a.tab_first = reinterpret_cast<const int64_t *>(c->ws + c->lay.first);
@@ -458,18 +467,141 @@ sclbm_status sclbm_step(sclbm_ctx *c, int64_t nsteps) {
     }
     a.g = c->cfg.g_ab;
     for (int k = 0; k < 3; ++k) a.xc[k] = c->geom.xc[k];
+    return a;
+}
+
+// Enqueue nsteps launches starting from buffer parity `par` (no host state change).
+hipError_t enqueue_steps(sclbm_ctx *c, int64_t nsteps, int par) {
+    StepArgs a = base_args(c);
     for (int64_t t = 0; t < nsteps; ++t) {
-        a.src = c->fbuf(c->par);
-        a.dst = c->fbuf(1 - c->par);
-        a.ref_src = c->refbuf(c->par);
-        a.ref_dst = c->refbuf(1 - c->par);
-        a.clk_in = c->clock() + c->par;
-        a.clk_out = c->clock() + (1 - c->par);
+        a.src = c->fbuf(par);
+        a.dst = c->fbuf(1 - par);
+        a.ref_src = c->refbuf(par);
+        a.ref_dst = c->refbuf(1 - par);
+        a.clk_in = c->clock() + par;
+        a.clk_out = c->clock() + (1 - par);
         hipError_t e = launch_step_prec(c, a);
-        if (e != hipSuccess) return fail(SCLBM_EHIP, "step kernel: %s", hipGetErrorString(e));
-        c->par ^= 1;
-        c->n += 1;
+        if (e != hipSuccess) return e;
+        par ^= 1;
     }
+    return hipSuccess;
+}
+
+void drop_graph(sclbm_ctx *c) {
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    c->graph_steps = 0;
+    c->graph_par = -1;
+}
+
+}  // namespace
+
+sclbm_status sclbm_step(sclbm_ctx *c, int64_t nsteps) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (nsteps < 0) return fail(SCLBM_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return SCLBM_OK;
+    if ((st = check_table(c, nsteps))) return st;
+    hipError_t e = enqueue_steps(c, nsteps, c->par);
+    if (e != hipSuccess) return fail(SCLBM_EHIP, "step kernel: %s", hipGetErrorString(e));
+    c->par ^= int(nsteps & 1);
+    c->n += nsteps;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_step_graph(sclbm_ctx *c, int64_t nsteps) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (nsteps < 2 || (nsteps & 1)) return fail(SCLBM_EINVAL, "nsteps must be even and >= 2");
+    if ((st = check_table(c, nsteps))) return st;
+    if (!c->graph_exec || c->graph_steps != nsteps || c->graph_par != c->par || c->graph_ty != c->tile_rows ||
+        c->graph_zc != c->zchunk) {
+        drop_graph(c);
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_steps(c, nsteps, c->par);
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) hipGraphDestroy(g);
+            return fail(SCLBM_EHIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->graph_exec = nullptr;
+            return fail(SCLBM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        c->graph_steps = nsteps;
+        c->graph_par = c->par;
+        c->graph_ty = c->tile_rows;
+        c->graph_zc = c->zchunk;
+    }
+    HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+    c->n += nsteps;  // even: the parity is unchanged
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk, float *best_ms) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (trial_steps < 1 || trial_steps > 100000) return fail(SCLBM_EINVAL, "trial_steps must be in [1, 100000]");
+    if ((st = check_table(c, int64_t(trial_steps) + 1))) return st;
+    const int ty_keep = c->tile_rows, zc_keep = c->zchunk;
+    const int64_t n0 = c->n;
+    const int par0 = c->par;
+    hipEvent_t ev0, ev1;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    float best = -1.0f;
+    int bty = ty_keep, bzc = zc_keep;
+    const int tys[2] = {4, 8};
+    const int zcs[6] = {2, 4, 8, 16, 32, 64};
+    sclbm_status result = SCLBM_OK;
+    for (int ti = 0; ti < 2 && result == SCLBM_OK; ++ti)
+        for (int zi = 0; zi < 6 && result == SCLBM_OK; ++zi) {
+            if (zcs[zi] > c->cfg.nz && zi > 0 && zcs[zi - 1] >= c->cfg.nz) continue;
+            c->tile_rows = tys[ti];
+            c->zchunk = std::min(zcs[zi], c->cfg.nz);
+            int64_t clk[2] = {n0, n0};
+            hipError_t e = hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = enqueue_steps(c, 1, par0 ^ 0);  // warm-up (reads row n0)
+            if (e == hipSuccess) e = hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev0, c->stream);
+            if (e == hipSuccess) e = enqueue_steps(c, trial_steps, par0);
+            if (e == hipSuccess) e = hipEventRecord(ev1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (e != hipSuccess) {
+                result = fail(SCLBM_EHIP, "autotune: %s", hipGetErrorString(e));
+                break;
+            }
+            ms /= float(trial_steps);
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                bty = c->tile_rows;
+                bzc = c->zchunk;
+            }
+        }
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+    // restore the time; the populations hold trial results
+    int64_t clk[2] = {n0, n0};
+    HIP_TRY(hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->n = n0;
+    c->par = par0;
+    if (result != SCLBM_OK) {
+        c->tile_rows = ty_keep;
+        c->zchunk = zc_keep;
+        return result;
+    }
+    c->tile_rows = bty;
+    c->zchunk = bzc;
+    drop_graph(c);
+    if (tile_rows) *tile_rows = bty;
+    if (zchunk) *zchunk = bzc;
+    if (best_ms) *best_ms = best;
     return SCLBM_OK;
 }
 
@@ -644,6 +776,7 @@ sclbm_status sclbm_load(sclbm_ctx *c, const void *host_buf, size_t bytes) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->par = 0;
     c->n = h.n;
+    drop_graph(c);
     return SCLBM_OK;
 }
 
@@ -654,6 +787,7 @@ sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk) {
     if (zchunk < 1) return fail(SCLBM_EINVAL, "zchunk must be >= 1");
     c->tile_rows = tile_rows;
     c->zchunk = std::min<int32_t>(zchunk, c->cfg.nz);
+    drop_graph(c);
     return SCLBM_OK;
 }
 

@@ -1,0 +1,100 @@
+"""GPU checks of the batched ensemble: several independent boxes in one launch
+per step, the hipGraph-captured step loop, and the autotuner (through the C ABI).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_09972_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_09972_amd as sc
+    sc.load()
+    return sc
+
+
+def ou_tables(n, nbox, steps, seed0=1000):
+    return [wl.ou_gradient_table(seed0 + b, n, steps, mach=0.1 + 0.05 * b) for b in range(nbox)]
+
+
+def test_ensemble_equals_independent_boxes(sc):
+    """Every box of a 3-box ensemble is bit-identical to the same box run alone,
+    and box 1 matches the oracle."""
+    n, nbox, steps, R = 24, 3, 40, 5.0
+    tabs = ou_tables(n, nbox, steps)
+    ens = sc.Lattice(n, n, n, nbox=nbox, bc="ghost", prec="f64", table_len=steps, g_ab=wl.G_AB,
+                     rho_b=wl.ghost_densities(R))
+    for b in range(nbox):
+        ens.init_droplet(ens.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0], box=b)
+        ens.set_gradient_table(tabs[b], 0, box=b)
+    ens.step(steps)
+    state = ens.save()[64:]
+    per_box = state.size // nbox
+    for b in range(nbox):
+        one = sc.Lattice(n, n, n, bc="ghost", prec="f64", table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
+        one.init_droplet(one.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0])
+        one.set_gradient_table(tabs[b], 0)
+        one.step(steps)
+        assert np.array_equal(one.save()[64:], state[b * per_box:(b + 1) * per_box]), b
+    o = oracle.Oracle(n, n, n, periodic=False, g=wl.G_AB, rho_b=wl.ghost_densities(R))
+    o.init_droplet(o.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[1][0])
+    o.run(steps, tabs[1])
+    ra, rb, _ = (t.cpu().numpy() for t in ens.fields(box=1))
+    oa, ob, _ = o.fields()
+    assert max(np.max(np.abs(ra - oa) / oa), np.max(np.abs(rb - ob) / ob)) <= 1e-11
+
+
+def test_graph_replays_match_eager(sc):
+    """A captured 10-step loop replayed five times, with eager work and
+    synchronisations between replays, equals eager stepping after every replay."""
+    n, nbox, steps, R = 20, 2, 60, 4.0
+    tabs = ou_tables(n, nbox, steps, seed0=77)
+
+    def make():
+        lat = sc.Lattice(n, n, n, nbox=nbox, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB,
+                         rho_b=wl.ghost_densities(R))
+        for b in range(nbox):
+            lat.init_droplet(lat.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0], box=b)
+            lat.set_gradient_table(tabs[b], 0, box=b)
+        return lat
+
+    g, e = make(), make()
+    for rep in range(5):
+        g.step_graph(10)
+        e.step(10)
+        # eager work on the graph's context between replays
+        g.totals()
+        g.synchronize()
+        assert g.step_count == e.step_count == 10 * (rep + 1)
+        assert np.array_equal(g.save(), e.save()), rep
+    # odd eager step flips the buffer parity: the graph is recaptured, still exact
+    g.step(1)
+    e.step(1)
+    g.step_graph(2)
+    e.step(2)
+    assert np.array_equal(g.save(), e.save())
+
+
+def test_autotune_keeps_results(sc):
+    n, steps, R = 40, 30, 8.0
+    A = wl.simple_shear(0.002)
+    lat = sc.Lattice(n, n, n, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
+    lat.set_gradient_table(np.tile(A, (steps, 1)), 0)
+    ty, zc, ms = sc.sclbm_autotune(lat.ctx, 3)
+    assert ty in (4, 8) and 1 <= zc <= n and ms > 0
+    assert lat.get_launch() == (ty, zc)
+    assert lat.step_count == 0
+    lat.init_droplet(lat.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
+    lat.step(steps)
+    ref = sc.Lattice(n, n, n, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
+    ref.set_gradient_table(np.tile(A, (steps, 1)), 0)
+    ref.init_droplet(ref.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
+    ref.step(steps)
+    assert np.array_equal(lat.save(), ref.save())
