@@ -168,6 +168,10 @@ sclbm_status sclbm_totals(sclbm_ctx *ctx, int32_t box, double mass[2], double mo
  * copy once). */
 sclbm_status sclbm_droplet_moments(sclbm_ctx *ctx, int32_t box, double *dev_out10);
 
+/* The same 10 moments for every box in one pass, dev_out[nbox][10] (device).
+ * Does not synchronise. */
+sclbm_status sclbm_droplet_moments_all(sclbm_ctx *ctx, double *dev_out);
+
 /* Droplet statistics from 10 indicator moments about `center` (host only, no
  * GPU work): covariance, its eigenvalues by the closed-form trigonometric
  * method for symmetric 3x3 matrices, semi-axes, deformation (Sec. 2 Eq. 4). */
@@ -201,6 +205,18 @@ sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t 
  * must cover steps n .. n + trial_steps.  Synchronises. */
 sclbm_status sclbm_autotune(sclbm_ctx *ctx, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk,
                             float *best_ms);
+
+/* Maffettone-Minale morphology tensor (Sec. 2 Eqs. 1, 2, 5) for ntraj
+ * trajectories on the GPU, one thread each, FP64 classical RK4 with `substeps`
+ * steps per table row and A(t) linear between rows; M = I is the sphere of the
+ * reference radius.  dev_A: [ntraj][nrows][9] velocity gradients in table time
+ * units; tau_d = eta_s R / sigma in the same units; chi the viscosity ratio;
+ * dev_M0: [ntraj][9] initial tensors or NULL for I; dev_M: [ntraj][nrec][9] with
+ * nrec = 1 + (nrows - 1) / record_every, record r at time r * record_every.
+ * Needs no context; enqueues on hip_stream (NULL = null stream). */
+sclbm_status sclbm_mm_integrate(const double *dev_A, int64_t ntraj, int64_t nrows, double tau_d, double chi,
+                                int32_t substeps, int32_t record_every, const double *dev_M0, double *dev_M,
+                                void *hip_stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *sclbm_last_error(void);

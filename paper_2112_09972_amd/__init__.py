@@ -52,7 +52,7 @@ EXPORTS = [
     "sclbm_set_gradient_table", "sclbm_step", "sclbm_get_step", "sclbm_fields", "sclbm_totals",
     "sclbm_droplet_moments", "sclbm_droplet_from_moments", "sclbm_droplet", "sclbm_velocity_error",
     "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch",
-    "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune",
+    "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune", "sclbm_droplet_moments_all", "sclbm_mm_integrate",
 ]
 
 
@@ -79,6 +79,8 @@ def _load_library():
         "sclbm_fields": [P, I32, P, P, P],
         "sclbm_totals": [P, I32, dp, dp],
         "sclbm_droplet_moments": [P, I32, P],
+        "sclbm_droplet_moments_all": [P, P],
+        "sclbm_mm_integrate": [P, I64, I64, D, D, I32, I32, P, P, P],
         "sclbm_droplet_from_moments": [dp, dp, I64, ctypes.POINTER(sclbm_droplet_stats)],
         "sclbm_droplet": [P, I32, ctypes.POINTER(sclbm_droplet_stats)],
         "sclbm_velocity_error": [P, I32, dp, dp],
@@ -202,6 +204,10 @@ def sclbm_droplet_moments(ctx, box, dev_out_ptr):
     _check(_lib.sclbm_droplet_moments(ctx, box, ctypes.c_void_p(dev_out_ptr)))
 
 
+def sclbm_droplet_moments_all(ctx, dev_out_ptr):
+    _check(_lib.sclbm_droplet_moments_all(ctx, ctypes.c_void_p(dev_out_ptr)))
+
+
 def sclbm_droplet_from_moments(moments, center, step=0) -> dict:
     out = sclbm_droplet_stats()
     _check(_lib.sclbm_droplet_from_moments(_dvec(moments, 10), _dvec(center, 3), int(step), ctypes.byref(out)))
@@ -243,6 +249,27 @@ def sclbm_get_launch(ctx):
     z = ctypes.c_int32()
     _check(_lib.sclbm_get_launch(ctx, ctypes.byref(t), ctypes.byref(z)))
     return t.value, z.value
+
+
+def sclbm_mm_integrate(dev_A_ptr, ntraj, nrows, tau_d, chi, substeps, record_every, dev_M0_ptr, dev_M_ptr, stream):
+    _check(_lib.sclbm_mm_integrate(ctypes.c_void_p(dev_A_ptr), int(ntraj), int(nrows), float(tau_d), float(chi),
+                                   int(substeps), int(record_every), ctypes.c_void_p(dev_M0_ptr) if dev_M0_ptr else None,
+                                   ctypes.c_void_p(dev_M_ptr), ctypes.c_void_p(stream)))
+
+
+def mm_integrate(A_rows, tau_d, chi=1.0, substeps=1, record_every=1, M0=None, device="cuda:0"):
+    """Torch convenience wrapper: A_rows (ntraj, nrows, 9) -> M (ntraj, nrec, 3, 3), on the GPU."""
+    import torch
+    A = torch.as_tensor(np.ascontiguousarray(A_rows, dtype=np.float64)).to(device)
+    ntraj, nrows = A.shape[0], A.shape[1]
+    nrec = 1 + (nrows - 1) // record_every
+    out = torch.empty((ntraj, nrec, 9), dtype=torch.float64, device=device)
+    m0 = None if M0 is None else torch.as_tensor(np.ascontiguousarray(M0, dtype=np.float64)).to(device)
+    stream = torch.cuda.current_stream(device)
+    sclbm_mm_integrate(A.data_ptr(), ntraj, nrows, tau_d, chi, substeps, record_every,
+                       m0.data_ptr() if m0 is not None else None, out.data_ptr(), stream.cuda_stream)
+    stream.synchronize()
+    return out.reshape(ntraj, nrec, 3, 3)
 
 
 def sclbm_last_error() -> str:
@@ -380,6 +407,11 @@ class Lattice:
     def droplet_moments(self, out, box=0):
         """Enqueue the 10 indicator moments of ``box`` into the device tensor ``out``."""
         sclbm_droplet_moments(self.ctx, box, out.data_ptr())
+
+    def droplet_moments_all(self, out):
+        """Enqueue the 10 indicator moments of every box into the device tensor out[nbox][10]."""
+        assert out.shape == (self.nbox, 10) and out.is_contiguous()
+        sclbm_droplet_moments_all(self.ctx, out.data_ptr())
 
     def velocity_error(self, A, box=0) -> float:
         return sclbm_velocity_error(self.ctx, box, A)

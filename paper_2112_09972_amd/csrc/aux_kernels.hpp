@@ -12,7 +12,8 @@
 
 namespace sclbm {
 
-constexpr int NRED_BLOCKS = 512;
+constexpr int NRED_BLOCKS = 512;        // workgroups of the single-box diagnostic reductions
+constexpr int NRED_MAX_PER_BOX = 1024;  // workgroups per box of the statistics reduction
 constexpr int NRED_THREADS = 256;
 constexpr int NSTAT = 16;  // mass 2, momentum 3, S0, S1 3, S2 6, bad-node count
 
@@ -191,9 +192,13 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[K], double *out /
 
 // Per-workgroup partials of: mass A, mass B, momentum (3), indicator moments
 // S0, S1 (3), S2 (6) about the box centre, and the count of bad nodes.
+// Grid (blocks per box, boxes): box b0 + blockIdx.y, partials [box][block][NSTAT].
 template <int P>
 __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::S *f, const __half *ref, BoxGeom g,
-                                                        double *partial) {
+                                                        int b0, double *partial) {
+    const int box = b0 + blockIdx.y;
+    f += (int64_t)box * 2 * Q * g.nnode;
+    if (Prec<P>::DEV) ref += (int64_t)box * 2 * g.nnode;
     double v[NSTAT];
 #pragma unroll
     for (int c = 0; c < NSTAT; ++c) v[c] = 0.0;
@@ -223,7 +228,7 @@ __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::
             v[14] += dz * dz;
         }
     }
-    block_reduce_store<NSTAT>(v, partial + (int64_t)blockIdx.x * NSTAT);
+    block_reduce_store<NSTAT>(v, partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * NSTAT);
 }
 
 // Partials of sum |u - A d|^2 and sum |A d|^2 (Sec. 4 Eq. 16).
@@ -244,9 +249,12 @@ __global__ __launch_bounds__(NRED_THREADS) void k_e0(const double *u, BoxGeom g,
     block_reduce_store<2>(v, partial + (int64_t)blockIdx.x * 2);
 }
 
-// Fixed-order sum of nblk partials of K values each.
+// Fixed-order sum of nblk partials of K values each; workgroup b handles the
+// partials of box b ([b][nblk][K] -> out[b][K]).
 template <int K>
 __global__ __launch_bounds__(NRED_THREADS) void k_final(const double *partial, int nblk, double *out) {
+    partial += (int64_t)blockIdx.x * nblk * K;
+    out += (int64_t)blockIdx.x * K;
     double v[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) v[c] = 0.0;

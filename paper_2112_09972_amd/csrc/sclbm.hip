@@ -12,6 +12,7 @@
 
 #include "aux_kernels.hpp"
 #include "lattice.hpp"
+#include "mm_kernel.hpp"
 #include "sclbm.h"
 #include "step_kernel.hpp"
 
@@ -77,6 +78,15 @@ bool config_ok(const sclbm_config *c, std::string &why) {
     return true;
 }
 
+// Workgroups per box of the statistics reduction: about 2048 nodes each, at
+// least enough to fill the chip when all boxes are reduced together.
+size_t stats_blocks(const sclbm_config *c) {
+    const size_t N = size_t(c->nx) * c->ny * c->nz;
+    size_t b = std::max<size_t>(1, N / 2048);
+    b = std::max<size_t>(b, (1024 + c->nbox - 1) / c->nbox);
+    return std::min<size_t>(b, NRED_MAX_PER_BOX);
+}
+
 Layout make_layout(const sclbm_config *c) {
     Layout L{};
     const size_t N = size_t(c->nx) * c->ny * c->nz;
@@ -90,8 +100,8 @@ Layout make_layout(const sclbm_config *c) {
     L.atab = off; off += round_up(size_t(c->nbox) * size_t(c->bc == SCLBM_BC_GHOST ? c->table_len : 0) * 9 * 8);
     L.first = off; off += round_up(size_t(c->nbox) * 8);
     L.clock = off; off += round_up(2 * 8);
-    L.partial = off; off += round_up(size_t(NRED_BLOCKS) * NSTAT * 8);
-    L.result = off; off += round_up(NSTAT * 8);
+    L.partial = off; off += round_up(std::max<size_t>(size_t(NRED_BLOCKS), size_t(c->nbox) * stats_blocks(c)) * NSTAT * 8);
+    L.result = off; off += round_up(size_t(c->nbox) * NSTAT * 8);
     L.diag = off; off += round_up(5 * N * 8);
     L.total = off;
     return L;
@@ -282,20 +292,20 @@ sclbm_status reduce_final(sclbm_ctx *c, int nblk, double *host_out) {
     return SCLBM_OK;
 }
 
-// Launch the FP64 partial statistics of one box at time n; final values go to
-// c->result() (device) after k_final.
-sclbm_status launch_stats(sclbm_ctx *c, int32_t box) {
+// Launch the FP64 statistics of boxes [b0, b0 + nb) at time n; the final 16
+// values of box b0 + i go to c->result() + 16 i (device).
+sclbm_status launch_stats(sclbm_ctx *c, int32_t b0, int32_t nb) {
+    const int bpb = int(stats_blocks(&c->cfg));
     hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
         using S = typename Prec<P>::S;
-        const S *f = reinterpret_cast<const S *>(c->fbuf(c->par)) + size_t(box) * 2 * Q * size_t(c->N);
-        hipLaunchKernelGGL((k_stats<P>), dim3(NRED_BLOCKS), dim3(NRED_THREADS), 0, c->stream, f,
-                           c->box_ref(c->par, box), c->geom, c->partial());
+        const S *f = reinterpret_cast<const S *>(c->fbuf(c->par));
+        hipLaunchKernelGGL((k_stats<P>), dim3(bpb, nb), dim3(NRED_THREADS), 0, c->stream, f, c->refbuf(c->par),
+                           c->geom, b0, c->partial());
         return hipGetLastError();
     });
     if (e != hipSuccess) return fail(SCLBM_EHIP, "stats kernel: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL((k_final<NSTAT>), dim3(1), dim3(NRED_THREADS), 0, c->stream, c->partial(), NRED_BLOCKS,
-                       c->result());
+    hipLaunchKernelGGL((k_final<NSTAT>), dim3(nb), dim3(NRED_THREADS), 0, c->stream, c->partial(), bpb, c->result());
     HIP_LAUNCHED();
     return SCLBM_OK;
 }
@@ -626,7 +636,7 @@ sclbm_status sclbm_totals(sclbm_ctx *c, int32_t box, double mass[2], double mome
     if (st) return st;
     if ((st = check_box(c, box, false))) return st;
     if (!mass || !momentum) return fail(SCLBM_EINVAL, "null output");
-    if ((st = launch_stats(c, box))) return st;
+    if ((st = launch_stats(c, box, 1))) return st;
     double r[NSTAT];
     HIP_TRY(hipMemcpyAsync(r, c->result(), sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -644,8 +654,18 @@ sclbm_status sclbm_droplet_moments(sclbm_ctx *c, int32_t box, double *dev_out10)
     if (st) return st;
     if ((st = check_box(c, box, false))) return st;
     if (!dev_out10) return fail(SCLBM_EINVAL, "null output");
-    if ((st = launch_stats(c, box))) return st;
+    if ((st = launch_stats(c, box, 1))) return st;
     HIP_TRY(hipMemcpyAsync(dev_out10, c->result() + 5, 10 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_droplet_moments_all(sclbm_ctx *c, double *dev_out) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!dev_out) return fail(SCLBM_EINVAL, "null output");
+    if ((st = launch_stats(c, 0, c->cfg.nbox))) return st;
+    HIP_TRY(hipMemcpy2DAsync(dev_out, 10 * sizeof(double), c->result() + 5, NSTAT * sizeof(double), 10 * sizeof(double),
+                             size_t(c->cfg.nbox), hipMemcpyDeviceToDevice, c->stream));
     return SCLBM_OK;
 }
 
@@ -683,7 +703,7 @@ sclbm_status sclbm_droplet(sclbm_ctx *c, int32_t box, sclbm_droplet_stats *out) 
     if (st) return st;
     if ((st = check_box(c, box, false))) return st;
     if (!out) return fail(SCLBM_EINVAL, "null output");
-    if ((st = launch_stats(c, box))) return st;
+    if ((st = launch_stats(c, box, 1))) return st;
     double r[NSTAT];
     HIP_TRY(hipMemcpyAsync(r, c->result(), sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -706,6 +726,20 @@ sclbm_status sclbm_velocity_error(sclbm_ctx *c, int32_t box, const double A[9], 
     if ((st = reduce_final<2>(c, NRED_BLOCKS, r))) return st;
     if (!(r[1] > 0.0)) return fail(SCLBM_EINVAL, "the imposed flow is zero on this box");
     *e0 = std::sqrt(r[0]) / std::sqrt(r[1]);
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_mm_integrate(const double *dev_A, int64_t ntraj, int64_t nrows, double tau_d, double chi,
+                                int32_t substeps, int32_t record_every, const double *dev_M0, double *dev_M,
+                                void *hip_stream) {
+    if (!dev_A || !dev_M) return fail(SCLBM_EINVAL, "null table or output");
+    if (ntraj < 1 || nrows < 1) return fail(SCLBM_EINVAL, "need ntraj >= 1 and nrows >= 1");
+    if (!(tau_d > 0.0) || !(chi > 0.0)) return fail(SCLBM_EINVAL, "need tau_d > 0 and chi > 0");
+    if (substeps < 1 || record_every < 1) return fail(SCLBM_EINVAL, "need substeps >= 1 and record_every >= 1");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    hipLaunchKernelGGL(k_mm, dim3(unsigned((ntraj + 63) / 64)), dim3(64), 0, s, dev_A, ntraj, nrows, tau_d, chi,
+                       int(substeps), int(record_every), dev_M0, dev_M);
+    HIP_LAUNCHED();
     return SCLBM_OK;
 }
 

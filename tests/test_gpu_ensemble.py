@@ -98,3 +98,25 @@ def test_autotune_keeps_results(sc):
     ref.init_droplet(ref.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
     ref.step(steps)
     assert np.array_equal(lat.save(), ref.save())
+
+
+def test_moments_of_all_boxes_in_one_pass(sc):
+    import torch
+    n, nbox, steps, R = 24, 4, 20, 5.0
+    tabs = ou_tables(n, nbox, steps, seed0=300)
+    lat = sc.Lattice(n, n, n, nbox=nbox, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB,
+                     rho_b=wl.ghost_densities(R))
+    for b in range(nbox):
+        lat.init_droplet(lat.xc, R + 0.5 * b, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0], box=b)
+        lat.set_gradient_table(tabs[b], 0, box=b)
+    lat.step(steps)
+    allm = torch.zeros((nbox, 10), dtype=torch.float64, device=lat.device)
+    lat.droplet_moments_all(allm)
+    one = torch.zeros(10, dtype=torch.float64, device=lat.device)
+    for b in range(nbox):
+        lat.droplet_moments(one, box=b)
+        lat.synchronize()
+        assert torch.equal(allm[b], one), b
+        ra, rb, _ = (t.cpu().numpy() for t in lat.fields(box=b))
+        ref = oracle.droplet_moments(ra, rb, lat.xc)
+        assert np.allclose(allm[b].cpu().numpy(), ref, rtol=1e-12, atol=1e-9)
