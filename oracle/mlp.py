@@ -89,9 +89,11 @@ def mse(y, t) -> float:
     return float(np.mean(d * d))
 
 
-def backward(flat, x, t, widths=WIDTHS, round_hidden=None):
+def backward(flat, x, t, widths=WIDTHS, round_hidden=None, round_grad=None):
     """Loss and gradient of the mean squared error with respect to the flat
-    parameter vector (chain rule, layer by layer from the output)."""
+    parameter vector (chain rule, layer by layer from the output).
+    `round_hidden` as in forward; `round_grad`, if given, is applied to the
+    gradient of every hidden pre-activation (a storage format, as above)."""
     y, hs = forward(flat, x, widths, round_hidden)
     ps = unflatten(flat, widths)
     n, nout = y.shape
@@ -105,6 +107,8 @@ def backward(flat, x, t, widths=WIDTHS, round_hidden=None):
         if l > 0:
             dh = dz @ ps[2 * l]
             dz = dh * (h > 0.0)
+            if round_grad is not None:
+                dz = round_grad(dz)
     return mse(y, t), flatten(grads)
 
 

@@ -53,6 +53,10 @@ EXPORTS = [
     "sclbm_droplet_moments", "sclbm_droplet_from_moments", "sclbm_droplet", "sclbm_velocity_error",
     "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch",
     "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune", "sclbm_droplet_moments_all", "sclbm_mm_integrate",
+    # droplet-shape surrogate (sclmlp.h)
+    "sclmlp_workspace_bytes", "sclmlp_create", "sclmlp_destroy", "sclmlp_set_params", "sclmlp_get_params",
+    "sclmlp_get_grads", "sclmlp_set_normalization", "sclmlp_predict", "sclmlp_gradients", "sclmlp_adam",
+    "sclmlp_train_step", "sclmlp_get_step", "sclmlp_bad_rows", "sclmlp_last_error",
 ]
 
 
@@ -89,13 +93,27 @@ def _load_library():
         "sclbm_load": [P, P, ctypes.c_size_t],
         "sclbm_set_launch": [P, I32, I32],
         "sclbm_get_launch": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "sclmlp_workspace_bytes": [I64, ctypes.POINTER(ctypes.c_size_t)],
+        "sclmlp_create": [I64, P, ctypes.c_size_t, P, ctypes.POINTER(P)],
+        "sclmlp_destroy": [P],
+        "sclmlp_set_params": [P, P],
+        "sclmlp_get_params": [P, P],
+        "sclmlp_get_grads": [P, P],
+        "sclmlp_set_normalization": [P, P, P, P, P],
+        "sclmlp_predict": [P, P, I64, P],
+        "sclmlp_gradients": [P, P, P, P, I64, I64, P],
+        "sclmlp_adam": [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
+        "sclmlp_train_step": [P, P, P, P, I64, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
+        "sclmlp_get_step": [P, ctypes.POINTER(I64)],
+        "sclmlp_bad_rows": [P, ctypes.POINTER(I64)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
-    lib.sclbm_last_error.argtypes = []
-    lib.sclbm_last_error.restype = ctypes.c_char_p
+    for name in ("sclbm_last_error", "sclmlp_last_error"):
+        getattr(lib, name).argtypes = []
+        getattr(lib, name).restype = ctypes.c_char_p
     return lib
 
 

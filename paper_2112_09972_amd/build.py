@@ -1,4 +1,5 @@
-"""Build step of the HIP library: compiles ``csrc/sclbm.hip`` for gfx950 into
+"""Build step of the HIP library: compiles ``csrc/sclbm.hip`` (lattice Boltzmann
+solver) and ``csrc/sclmlp.hip`` (droplet-shape surrogate) for gfx950 into one
 ``libsclbm.so`` next to this file (in-tree, so it travels with the source tree).
 
 Usage: ``python -m paper_2112_09972_amd.build`` or ``build_library()``.
@@ -12,7 +13,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRC = os.path.join(PKG, "csrc", "sclbm.hip")
+SRCS = [os.path.join(PKG, "csrc", "sclbm.hip"), os.path.join(PKG, "csrc", "sclmlp.hip")]
 LIB = os.path.join(PKG, "libsclbm.so")
 ARCH = "gfx950"
 
@@ -38,7 +39,7 @@ def hipcc() -> str:
 def build_library(verbose: bool = False) -> str:
     """Compile the library (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp, SRC]
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp] + SRCS
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l and l.strip())
     if res.returncode != 0:

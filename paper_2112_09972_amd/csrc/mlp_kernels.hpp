@@ -1,0 +1,404 @@
+// Kernels of the droplet-shape surrogate: a 576 -> 512 -> 512 -> 512 -> 3 ReLU
+// perceptron from a window of the velocity-gradient history (64 samples of A(t),
+// Sec. 3) to the droplet's three semi-axes (Sec. 2 Eq. 4 takes D from them).
+//
+// Arithmetic: BF16 operands, FP32 accumulation on the gfx950 matrix cores
+// (v_mfma_f32_32x32x16_bf16), FP32 biases, FP32 master weights and Adam moments.
+// Every product is "NT": C[m][n] = sum_k A[m][k] B[n][k] with both operands
+// contiguous in k, so each lane's MFMA fragment is one 16-byte load.  The
+// forward pass writes every hidden activation twice, [batch][unit] for the next
+// layer's product and [unit][batch] for the weight gradient's product (whose
+// contraction runs over the batch); the backward pass does the same for the
+// pre-activation gradients, and Adam keeps a transposed BF16 copy of the hidden
+// weights for the input-gradient products.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sclmlp {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int NIN = 576;    // 64 samples x 9 gradient entries
+constexpr int NHID = 512;
+constexpr int NOUT = 3;
+constexpr int NLAYER = 4;
+constexpr int ROW_ALIGN = 128;  // the batch is padded to this many rows inside the library
+
+// flat FP32 parameter vector: W1 [512][576], b1, W2 [512][512], b2, W3, b3, W4 [3][512], b4
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + NHID * NIN;
+constexpr int OFF_W2 = OFF_B1 + NHID;
+constexpr int OFF_B2 = OFF_W2 + NHID * NHID;
+constexpr int OFF_W3 = OFF_B2 + NHID;
+constexpr int OFF_B3 = OFF_W3 + NHID * NHID;
+constexpr int OFF_W4 = OFF_B3 + NHID;
+constexpr int OFF_B4 = OFF_W4 + NOUT * NHID;
+constexpr int NPARAM = OFF_B4 + NOUT;
+static_assert(NPARAM == 822275, "parameter count");
+
+// ---------------------------------------------------------------------------------------------
+// GEMM: C = A B^T with an epilogue.  A [M][K] (row stride lda), B [N][K] (ldb), K % 64 == 0.
+enum Epi { EPI_RELU = 0, EPI_MASK = 1, EPI_F32 = 2 };
+
+struct GemmArgs {
+    const bf16 *A, *B;
+    int M, N, K, lda, ldb;
+    const float *bias;   // EPI_RELU: per column n
+    const bf16 *mask;    // EPI_MASK: element (m, n) kept where mask > 0 (row stride ldmask)
+    int ldmask;
+    void *C;             // bf16 (RELU, MASK; may be null) or float (F32), row stride ldc
+    int ldc;
+    bf16 *CT;            // optional transposed bf16 copy, CT[n][m], row stride ldct
+    int ldct;
+};
+
+__device__ __forceinline__ uint4 ld16(const bf16 *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+template <int BM, int BN, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
+    constexpr int BK = 64, LDK = BK + 8;   // 16-byte pad per LDS row spreads the fragment reads over banks
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int FM = WM / 32, FN = WN / 32;
+    constexpr int CA = BM * 8 / 256, CB = BN * 8 / 256;
+    static_assert(FM >= 1 && FN >= 1 && CA >= 1 && CB >= 1, "tile");
+    __shared__ __attribute__((aligned(16))) bf16 As[BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * LDK];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    // XCD-aware order: consecutive workgroups go round-robin over the 8 XCDs; renumber so
+    // that the column tiles of one row tile share an XCD (and its L2 copy of the A rows).
+    const int ntn = gridDim.x, total = gridDim.x * gridDim.y;
+    int lin = blockIdx.y * ntn + blockIdx.x;
+    if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
+    const int m0 = (lin / ntn) * BM, n0 = (lin % ntn) * BN;
+
+    uint4 ra[CA], rb[CB];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < CA; ++i) {
+            const int c = tid + 256 * i, r = c >> 3, kc = (c & 7) * 8;
+            ra[i] = (m0 + r < g.M) ? ld16(g.A + (size_t)(m0 + r) * g.lda + k0 + kc) : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int c = tid + 256 * i, r = c >> 3, kc = (c & 7) * 8;
+            rb[i] = (n0 + r < g.N) ? ld16(g.B + (size_t)(n0 + r) * g.ldb + k0 + kc) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < CA; ++i) {
+            const int c = tid + 256 * i;
+            *reinterpret_cast<uint4 *>(As + (c >> 3) * LDK + (c & 7) * 8) = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+            const int c = tid + 256 * i;
+            *reinterpret_cast<uint4 *>(Bs + (c >> 3) * LDK + (c & 7) * 8) = rb[i];
+        }
+    };
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    const int nk = g.K / BK;
+    gload(0);
+    sstore();
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+        for (int s = 0; s < BK / 16; ++s) {
+            bf16x8 a[FM], b[FN];
+            const int kk = s * 16 + (lane >> 5) * 8;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * WM + i * 32 + (lane & 31)) * LDK + kk);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * WN + j * 32 + (lane & 31)) * LDK + kk);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nk) {
+            __syncthreads();
+            sstore();
+            __syncthreads();
+        }
+    }
+
+    // accumulator element 4q + j of a 32x32 fragment sits at row 8q + 4 (lane / 32) + j, column lane % 32
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = n0 + wn * WN + j * 32 + (lane & 31);
+            if (col >= g.N) continue;
+            float bias = 0.0f;
+            if (EPI == EPI_RELU) bias = g.bias[col];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row0 = m0 + wm * WM + i * 32 + 8 * q + 4 * (lane >> 5);
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = acc[i][j][4 * q + e];
+                    if (EPI == EPI_RELU) v[e] = fmaxf(v[e] + bias, 0.0f);
+                    if (EPI == EPI_MASK && row0 + e < g.M)
+                        v[e] = (float)g.mask[(size_t)(row0 + e) * g.ldmask + col] > 0.0f ? v[e] : 0.0f;
+                }
+                if (EPI == EPI_F32) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (row0 + e < g.M) static_cast<float *>(g.C)[(size_t)(row0 + e) * g.ldc + col] = v[e];
+                } else {
+                    bf16 h[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) h[e] = (bf16)v[e];
+                    if (g.C) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (row0 + e < g.M) static_cast<bf16 *>(g.C)[(size_t)(row0 + e) * g.ldc + col] = h[e];
+                    }
+                    if (g.CT) {
+                        bf16 *dst = g.CT + (size_t)col * g.ldct + row0;
+                        if (row0 + 3 < g.M) {
+                            bf16x4 p4 = {h[0], h[1], h[2], h[3]};
+                            *reinterpret_cast<bf16x4 *>(dst) = p4;
+                        } else {
+                            for (int e = 0; e < 4; ++e)
+                                if (row0 + e < g.M) dst[e] = h[e];
+                        }
+                    }
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Input preparation: gather (optional index), normalise, round to BF16; rows >= n are zero.
+// Tiles of 64 rows x 64 features, grid (NIN / 64, Mpad / 64).  A row whose index lies outside
+// [0, ndata) is treated as padding and counted in *bad.
+template <bool TRANSPOSED>
+__global__ __launch_bounds__(256) void k_prep(const float *win, const int32_t *index, int n, int ndata,
+                                              const float *shift, const float *scale, bf16 *X, bf16 *XT,
+                                              int Mpad, unsigned *bad) {
+    __shared__ bf16 tile[64][66];
+    const int c0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int c = c0 + tx;
+    const float sh = shift[c], sc = scale[c];
+    for (int r = ty; r < 64; r += 4) {
+        const int m = m0 + r;
+        float v = 0.0f;
+        if (m < n) {
+            const int64_t src = index ? (int64_t)index[m] : (int64_t)m;
+            if (src >= 0 && src < ndata) {
+                v = (win[src * NIN + c] - sh) * sc;
+            } else if (tx == 0 && blockIdx.x == 0) {
+                atomicAdd(bad, 1u);
+            }
+        }
+        const bf16 b = (bf16)v;
+        X[(size_t)m * NIN + c] = b;
+        if (TRANSPOSED) tile[r][tx] = b;
+    }
+    if (TRANSPOSED) {
+        __syncthreads();
+        for (int r = ty; r < 64; r += 4) XT[(size_t)(c0 + r) * Mpad + m0 + tx] = tile[tx][r];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Output layer (3 units, no activation): one wave per row, each lane 8 of the 512 inputs.
+// PREDICT: writes de-normalised semi-axes for rows < n.  Training: writes dY = 2 (y - t) / (3 n)
+// (zero on padding rows) and per-block sums of (y - t)^2 and of dY.  64 rows per block.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <bool PREDICT>
+__global__ __launch_bounds__(256) void k_out(const bf16 *H, const bf16 *W4, const float *b4, int n, const float *oshift,
+                                             const float *oscale, float *out, const float *targets,
+                                             const int32_t *index, int ndata, float *dY, double *partial) {
+    __shared__ double red[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float w[NOUT][8];
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(W4 + j * NHID + lane * 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[j][e] = (float)v[e];
+    }
+    double loss = 0.0, db[NOUT] = {0.0, 0.0, 0.0};
+    const float inv = n > 0 ? 2.0f / (3.0f * (float)n) : 0.0f;
+    for (int r = 0; r < 16; ++r) {
+        const int m = blockIdx.x * 64 + wave * 16 + r;
+        const bf16x8 h = *reinterpret_cast<const bf16x8 *>(H + (size_t)m * NHID + lane * 8);
+        float s[NOUT] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float hv = (float)h[e];
+#pragma unroll
+            for (int j = 0; j < NOUT; ++j) s[j] = fmaf(hv, w[j][e], s[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < NOUT; ++j) s[j] = wave_sum(s[j]) + b4[j];
+        if (PREDICT) {
+            if (m < n && lane < NOUT) {
+                const float y = lane == 0 ? s[0] : (lane == 1 ? s[1] : s[2]);
+                out[(size_t)m * NOUT + lane] = y / oscale[lane] + oshift[lane];
+            }
+        } else {
+            bool valid = m < n;
+            int64_t src = 0;
+            if (valid) {
+                src = index ? (int64_t)index[m] : (int64_t)m;
+                valid = src >= 0 && src < ndata;
+            }
+#pragma unroll
+            for (int j = 0; j < NOUT; ++j) {
+                const float t = valid ? (targets[src * NOUT + j] - oshift[j]) * oscale[j] : 0.0f;
+                const float d = valid ? s[j] - t : 0.0f;
+                const float g = d * inv;
+                if (lane == j) dY[(size_t)m * NOUT + j] = g;
+                loss += (double)d * (double)d;
+                db[j] += (double)g;
+            }
+        }
+    }
+    if (!PREDICT) {
+        if (lane == 0) {
+            red[wave][0] = loss;
+            for (int j = 0; j < NOUT; ++j) red[wave][1 + j] = db[j];
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double t = 0.0;
+            for (int q = 0; q < 4; ++q) t += red[q][threadIdx.x];
+            partial[blockIdx.x * 4 + threadIdx.x] = t;
+        }
+    }
+}
+
+// Fixed-order sum of the per-block partials: loss = sum (y - t)^2 / (3 n), db4 = sum dY.
+__global__ void k_loss_final(const double *partial, int nblocks, int n, double *loss, float *db4) {
+    const int j = threadIdx.x;
+    if (j >= 4) return;
+    double t = 0.0;
+    for (int b = 0; b < nblocks; ++b) t += partial[b * 4 + j];
+    if (j == 0) {
+        if (loss) *loss = n > 0 ? t / (3.0 * (double)n) : 0.0;
+    } else {
+        db4[j - 1] = (float)t;
+    }
+}
+
+// dZ3[m][k] = (sum_j dY[m][j] W4[j][k]) * (H3[m][k] > 0), written [m][k] and [k][m].
+// Tiles 64 x 64, grid (NHID / 64, Mpad / 64).
+__global__ __launch_bounds__(256) void k_out_back(const float *dY, const bf16 *W4, const bf16 *H, bf16 *dZ, bf16 *dZT,
+                                                  int Mpad) {
+    __shared__ bf16 tile[64][66];
+    const int k0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int k = k0 + tx;
+    const float w0 = (float)W4[k], w1 = (float)W4[NHID + k], w2 = (float)W4[2 * NHID + k];
+    for (int r = ty; r < 64; r += 4) {
+        const int m = m0 + r;
+        const float *d = dY + (size_t)m * NOUT;
+        float v = d[0] * w0 + d[1] * w1 + d[2] * w2;
+        v = (float)H[(size_t)m * NHID + k] > 0.0f ? v : 0.0f;
+        const bf16 b = (bf16)v;
+        dZ[(size_t)m * NHID + k] = b;
+        tile[r][tx] = b;
+    }
+    __syncthreads();
+    for (int r = ty; r < 64; r += 4) dZT[(size_t)(k0 + r) * Mpad + m0 + tx] = tile[tx][r];
+}
+
+// out[r * ors + j * ojs] = sum_m AT[r][m] * V[m][j]  (V == nullptr: ones, J == 1); one block per row.
+template <int J>
+__global__ __launch_bounds__(256) void k_rowdot(const bf16 *AT, int ld, int len, const float *V, float *out, int ors,
+                                                int ojs) {
+    __shared__ float red[4][J];
+    const int r = blockIdx.x;
+    float s[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) s[j] = 0.0f;
+    for (int m = threadIdx.x; m < len; m += 256) {
+        const float a = (float)AT[(size_t)r * ld + m];
+#pragma unroll
+        for (int j = 0; j < J; ++j) s[j] = V ? fmaf(a, V[(size_t)m * J + j], s[j]) : s[j] + a;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        s[j] = wave_sum(s[j]);
+        if (lane == 0) red[wave][j] = s[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < J) {
+        const int j = threadIdx.x;
+        out[(size_t)r * ors + j * ojs] = red[0][j] + red[1][j] + red[2][j] + red[3][j];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Adam on the FP32 master parameters, then the BF16 copies the products read.
+struct Seg {
+    int off, rows, cols;
+    bf16 *w;   // [rows][cols] copy, or null
+    bf16 *wt;  // [cols][rows] copy, or null
+};
+struct AdamArgs {
+    float *p;
+    const float *g;
+    float *m, *v;
+    int n;
+    int update;  // 0: only refresh the BF16 copies
+    float lr, beta1, beta2, eps, bc1, bc2;  // bc = 1 - beta^step
+    Seg seg[NLAYER];
+};
+
+__global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < a.n; i += gridDim.x * 256) {
+        float p = a.p[i];
+        if (a.update) {
+            const float g = a.g[i];
+            const float m = a.beta1 * a.m[i] + (1.0f - a.beta1) * g;
+            const float v = a.beta2 * a.v[i] + (1.0f - a.beta2) * g * g;
+            a.m[i] = m;
+            a.v[i] = v;
+            p -= a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+            a.p[i] = p;
+        }
+#pragma unroll
+        for (int s = 0; s < NLAYER; ++s) {
+            const Seg &q = a.seg[s];
+            const int o = i - q.off;
+            if (o >= 0 && o < q.rows * q.cols) {
+                const bf16 b = (bf16)p;
+                if (q.w) q.w[o] = b;
+                if (q.wt) q.wt[(size_t)(o % q.cols) * q.rows + o / q.cols] = b;
+            }
+        }
+    }
+}
+
+}  // namespace sclmlp
