@@ -76,12 +76,24 @@ sclbm_status sclmlp_predict(sclmlp_ctx *ctx, const float *dev_windows, int64_t n
 /* Forward and backward pass over a batch of n rows (1 <= n <= max_batch):
  * row m uses dev_windows[idx] and dev_targets[idx] (targets [.][3] FP32, in
  * semi-axis units) with idx = dev_index[m] (int32) or m when dev_index is NULL;
- * ndata is the number of rows of dev_windows / dev_targets.  A row whose index
- * lies outside [0, ndata) contributes nothing and is counted (sclmlp_bad_rows).
- * Leaves the gradient of the mean squared error of the normalised outputs in
- * the context; dev_loss (may be NULL) receives that loss as one FP64 value. */
+ * ndata is the number of rows of dev_windows / dev_targets.
+ *
+ * dev_sym (int32 per row, or NULL for none) applies a symmetry of the cubic
+ * box to the row's window: id s in [0, 48) names the signed permutation P with
+ * P[i][perm(i)] = sign(i), perm the (s / 8)-th permutation of (0, 1, 2) in
+ * lexicographic order and sign(i) = -1 where bit i of (s % 8) is set; every
+ * sample A of the window becomes P A P^T.  The droplet box (cube, D3Q19
+ * lattice, centred droplet, ghost velocity A (x - x_c)) is invariant under these
+ * maps, so the semi-axes (the targets) do not change: an exact augmentation.
+ *
+ * A row whose index lies outside [0, ndata), or whose symmetry id lies outside
+ * [0, 48), contributes nothing and is counted (sclmlp_bad_rows).  Leaves the
+ * gradient of the mean squared error of the normalised outputs, averaged over
+ * the n rows, in the context; dev_loss (may be NULL) receives that loss as one
+ * FP64 value. */
 sclbm_status sclmlp_gradients(sclmlp_ctx *ctx, const float *dev_windows, const float *dev_targets,
-                              const int32_t *dev_index, int64_t n, int64_t ndata, double *dev_loss);
+                              const int32_t *dev_index, const int32_t *dev_sym, int64_t n, int64_t ndata,
+                              double *dev_loss);
 
 /* One Adam step (bias-corrected) with the gradients in the context, then the
  * BF16 copies.  lr > 0, 0 <= beta1, beta2 < 1, eps > 0. */
@@ -89,13 +101,14 @@ sclbm_status sclmlp_adam(sclmlp_ctx *ctx, float lr, float beta1, float beta2, fl
 
 /* sclmlp_gradients followed by sclmlp_adam. */
 sclbm_status sclmlp_train_step(sclmlp_ctx *ctx, const float *dev_windows, const float *dev_targets,
-                               const int32_t *dev_index, int64_t n, int64_t ndata, float lr, float beta1,
-                               float beta2, float eps, double *dev_loss);
+                               const int32_t *dev_index, const int32_t *dev_sym, int64_t n, int64_t ndata,
+                               float lr, float beta1, float beta2, float eps, double *dev_loss);
 
 /* Adam steps taken since sclmlp_set_params. */
 sclbm_status sclmlp_get_step(const sclmlp_ctx *ctx, int64_t *step);
 
-/* Rows skipped for an out-of-range index since the context was created.  Synchronises. */
+/* Rows skipped for an out-of-range index or symmetry id since the context was
+ * created.  Synchronises. */
 sclbm_status sclmlp_bad_rows(sclmlp_ctx *ctx, int64_t *count);
 
 const char *sclmlp_last_error(void);

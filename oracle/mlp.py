@@ -139,6 +139,25 @@ def deformation(semi_axes) -> np.ndarray:
     return (a[..., 2] - a[..., 0]) / (a[..., 2] + a[..., 0])
 
 
+def cubic_symmetry(s: int) -> np.ndarray:
+    """Signed permutation matrix number s of the 48 symmetries of the cube:
+    P[i][perm(i)] = sign(i), perm = the (s // 8)-th permutation of (0, 1, 2) in
+    lexicographic order, sign(i) = -1 where bit i of s % 8 is set."""
+    import itertools
+    perm = list(itertools.permutations(range(3)))[s // 8]
+    P = np.zeros((3, 3))
+    for i in range(3):
+        P[i, perm[i]] = -1.0 if (s % 8) >> i & 1 else 1.0
+    return P
+
+
+def transform_window(window, s: int) -> np.ndarray:
+    """Every 3x3 sample A of a flattened window becomes P A P^T (P = cubic_symmetry(s))."""
+    P = cubic_symmetry(s)
+    A = np.asarray(window, dtype=np.float64).reshape(-1, 3, 3)
+    return np.matmul(np.matmul(P, A), P.T).reshape(np.shape(window))
+
+
 def round_bf16(x) -> np.ndarray:
     """Round float64 values to the nearest bfloat16 (ties to even) through float32:
     the float32 value first (round to nearest), then its 16 high bits with the

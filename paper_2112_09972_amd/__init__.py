@@ -101,9 +101,10 @@ def _load_library():
         "sclmlp_get_grads": [P, P],
         "sclmlp_set_normalization": [P, P, P, P, P],
         "sclmlp_predict": [P, P, I64, P],
-        "sclmlp_gradients": [P, P, P, P, I64, I64, P],
+        "sclmlp_gradients": [P, P, P, P, P, I64, I64, P],
         "sclmlp_adam": [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float],
-        "sclmlp_train_step": [P, P, P, P, I64, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, P],
+        "sclmlp_train_step": [P, P, P, P, P, I64, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              P],
         "sclmlp_get_step": [P, ctypes.POINTER(I64)],
         "sclmlp_bad_rows": [P, ctypes.POINTER(I64)],
     }

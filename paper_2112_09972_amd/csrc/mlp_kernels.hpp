@@ -190,25 +190,46 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Input preparation: gather (optional index), normalise, round to BF16; rows >= n are zero.
-// Tiles of 64 rows x 64 features, grid (NIN / 64, Mpad / 64).  A row whose index lies outside
-// [0, ndata) is treated as padding and counted in *bad.
+// Input preparation: gather (optional index), optional cubic symmetry of the box, normalise,
+// round to BF16; rows >= n are zero.  Tiles of 64 rows x 64 features, grid (NIN / 64, Mpad / 64).
+// A row whose index (or symmetry id) is out of range is treated as padding and counted in *bad.
+//
+// Symmetry id s in [0, 48): P = signed permutation with P[i][perm(i)] = sign(i), perm the
+// (s / 8)-th permutation of (0, 1, 2) in lexicographic order, sign(i) = -1 where bit i of s % 8
+// is set.  Every sample A of the window becomes P A P^T:  A'_ij = sign(i) sign(j) A_{perm(i) perm(j)}.
+__device__ __forceinline__ int sym_source(int s, int e, float &sgn) {
+    // e = 3 i + j within one 3 x 3 sample
+    const int i = e / 3, j = e - 3 * i;
+    const int pi = s >> 3;                       // 012 021 102 120 201 210
+    const int p0 = pi < 2 ? 0 : (pi < 4 ? 1 : 2);
+    const int p1 = (pi == 0 || pi == 5) ? 1 : ((pi == 1 || pi == 3) ? 2 : 0);
+    const int p2 = 3 - p0 - p1;
+    const int qi = i == 0 ? p0 : (i == 1 ? p1 : p2);
+    const int qj = j == 0 ? p0 : (j == 1 ? p1 : p2);
+    sgn = (((s >> i) ^ (s >> j)) & 1) ? -1.0f : 1.0f;
+    return 3 * qi + qj;
+}
+
 template <bool TRANSPOSED>
-__global__ __launch_bounds__(256) void k_prep(const float *win, const int32_t *index, int n, int ndata,
-                                              const float *shift, const float *scale, bf16 *X, bf16 *XT,
+__global__ __launch_bounds__(256) void k_prep(const float *win, const int32_t *index, const int32_t *sym, int n,
+                                              int ndata, const float *shift, const float *scale, bf16 *X, bf16 *XT,
                                               int Mpad, unsigned *bad) {
     __shared__ bf16 tile[64][66];
     const int c0 = blockIdx.x * 64, m0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int c = c0 + tx;
+    const int t9 = c / 9, e = c - 9 * t9;
     const float sh = shift[c], sc = scale[c];
     for (int r = ty; r < 64; r += 4) {
         const int m = m0 + r;
         float v = 0.0f;
         if (m < n) {
             const int64_t src = index ? (int64_t)index[m] : (int64_t)m;
-            if (src >= 0 && src < ndata) {
-                v = (win[src * NIN + c] - sh) * sc;
+            const int s = sym ? sym[m] : 0;
+            if (src >= 0 && src < ndata && s >= 0 && s < 48) {
+                float sgn = 1.0f;
+                const int f = s ? 9 * t9 + sym_source(s, e, sgn) : c;
+                v = (win[src * NIN + f] * sgn - sh) * sc;
             } else if (tx == 0 && blockIdx.x == 0) {
                 atomicAdd(bad, 1u);
             }
@@ -236,7 +257,8 @@ __device__ __forceinline__ float wave_sum(float v) {
 template <bool PREDICT>
 __global__ __launch_bounds__(256) void k_out(const bf16 *H, const bf16 *W4, const float *b4, int n, const float *oshift,
                                              const float *oscale, float *out, const float *targets,
-                                             const int32_t *index, int ndata, float *dY, double *partial) {
+                                             const int32_t *index, const int32_t *sym, int ndata, float *dY,
+                                             double *partial) {
     __shared__ double red[4][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float w[NOUT][8];
@@ -270,7 +292,8 @@ __global__ __launch_bounds__(256) void k_out(const bf16 *H, const bf16 *W4, cons
             int64_t src = 0;
             if (valid) {
                 src = index ? (int64_t)index[m] : (int64_t)m;
-                valid = src >= 0 && src < ndata;
+                const int sv = sym ? sym[m] : 0;
+                valid = src >= 0 && src < ndata && sv >= 0 && sv < 48;
             }
 #pragma unroll
             for (int j = 0; j < NOUT; ++j) {

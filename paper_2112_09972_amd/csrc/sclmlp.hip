@@ -303,19 +303,21 @@ sclbm_status sclmlp_predict(sclmlp_ctx *c, const float *dev_windows, int64_t n, 
     if (!dev_windows || !dev_out) return fail(SCLBM_EINVAL, "null buffer");
     TRY(use_device(c));
     const int Mp = (int)padded_rows(n);
-    k_prep<false><<<dim3(NIN / 64, Mp / 64), 256, 0, c->stream>>>(dev_windows, nullptr, (int)n, (int)n,
+    k_prep<false><<<dim3(NIN / 64, Mp / 64), 256, 0, c->stream>>>(dev_windows, nullptr, nullptr, (int)n, (int)n,
                                                                     c->in_shift(), c->in_scale(), c->at<bf16>(c->lay.x),
                                                                     nullptr, Mp, c->at<unsigned>(c->lay.bad));
     HIP_LAUNCHED();
     TRY(hidden_forward(c, Mp, false));
     k_out<true><<<Mp / 64, 256, 0, c->stream>>>(c->h(2), c->wb(3), c->P() + OFF_B4, (int)n, c->out_shift(),
-                                                c->out_scale(), dev_out, nullptr, nullptr, 0, nullptr, nullptr);
+                                                c->out_scale(), dev_out, nullptr, nullptr, nullptr, 0, nullptr,
+                                                nullptr);
     HIP_LAUNCHED();
     return SCLBM_OK;
 }
 
 sclbm_status sclmlp_gradients(sclmlp_ctx *c, const float *dev_windows, const float *dev_targets,
-                              const int32_t *dev_index, int64_t n, int64_t ndata, double *dev_loss) {
+                              const int32_t *dev_index, const int32_t *dev_sym, int64_t n, int64_t ndata,
+                              double *dev_loss) {
     if (!c) return fail(SCLBM_EINVAL, "null context");
     if (n < 1 || n > c->max_batch) return fail(SCLBM_EINVAL, "n = %lld outside [1, %lld]", (long long)n,
                                               (long long)c->max_batch);
@@ -330,13 +332,14 @@ sclbm_status sclmlp_gradients(sclmlp_ctx *c, const float *dev_windows, const flo
     float *dy = c->at<float>(c->lay.dy);
     double *partial = c->at<double>(c->lay.partial);
 
-    k_prep<true><<<dim3(NIN / 64, nb), 256, 0, c->stream>>>(dev_windows, dev_index, (int)n, (int)ndata,
+    k_prep<true><<<dim3(NIN / 64, nb), 256, 0, c->stream>>>(dev_windows, dev_index, dev_sym, (int)n, (int)ndata,
                                                              c->in_shift(), c->in_scale(), c->at<bf16>(c->lay.x),
                                                              c->at<bf16>(c->lay.xt), Mp, c->at<unsigned>(c->lay.bad));
     HIP_LAUNCHED();
     TRY(hidden_forward(c, Mp, true));
     k_out<false><<<nb, 256, 0, c->stream>>>(c->h(2), c->wb(3), c->P() + OFF_B4, (int)n, c->out_shift(),
-                                            c->out_scale(), nullptr, dev_targets, dev_index, (int)ndata, dy, partial);
+                                            c->out_scale(), nullptr, dev_targets, dev_index, dev_sym, (int)ndata, dy,
+                                            partial);
     HIP_LAUNCHED();
     k_loss_final<<<1, 64, 0, c->stream>>>(partial, nb, (int)n, dev_loss ? dev_loss : c->at<double>(c->lay.loss),
                                           G + OFF_B4);
@@ -396,12 +399,12 @@ sclbm_status sclmlp_adam(sclmlp_ctx *c, float lr, float beta1, float beta2, floa
 }
 
 sclbm_status sclmlp_train_step(sclmlp_ctx *c, const float *dev_windows, const float *dev_targets,
-                               const int32_t *dev_index, int64_t n, int64_t ndata, float lr, float beta1, float beta2,
-                               float eps, double *dev_loss) {
+                               const int32_t *dev_index, const int32_t *dev_sym, int64_t n, int64_t ndata, float lr,
+                               float beta1, float beta2, float eps, double *dev_loss) {
     if (!c) return fail(SCLBM_EINVAL, "null context");
     if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
         return fail(SCLBM_EINVAL, "Adam hyper-parameters out of range");
-    TRY(sclmlp_gradients(c, dev_windows, dev_targets, dev_index, n, ndata, dev_loss));
+    TRY(sclmlp_gradients(c, dev_windows, dev_targets, dev_index, dev_sym, n, ndata, dev_loss));
     return sclmlp_adam(c, lr, beta1, beta2, eps);
 }
 

@@ -75,17 +75,18 @@ def sclmlp_predict(ctx, windows, n, out):
     _check(_lib.sclmlp_predict(ctx, _ptr(windows), int(n), _ptr(out)))
 
 
-def sclmlp_gradients(ctx, windows, targets, index, n, ndata, loss=None):
-    _check(_lib.sclmlp_gradients(ctx, _ptr(windows), _ptr(targets), _ptr(index), int(n), int(ndata), _ptr(loss)))
+def sclmlp_gradients(ctx, windows, targets, index, sym, n, ndata, loss=None):
+    _check(_lib.sclmlp_gradients(ctx, _ptr(windows), _ptr(targets), _ptr(index), _ptr(sym), int(n), int(ndata),
+                                 _ptr(loss)))
 
 
 def sclmlp_adam(ctx, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     _check(_lib.sclmlp_adam(ctx, float(lr), float(beta1), float(beta2), float(eps)))
 
 
-def sclmlp_train_step(ctx, windows, targets, index, n, ndata, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
-    _check(_lib.sclmlp_train_step(ctx, _ptr(windows), _ptr(targets), _ptr(index), int(n), int(ndata), float(lr),
-                                  float(beta1), float(beta2), float(eps), _ptr(loss)))
+def sclmlp_train_step(ctx, windows, targets, index, sym, n, ndata, lr, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
+    _check(_lib.sclmlp_train_step(ctx, _ptr(windows), _ptr(targets), _ptr(index), _ptr(sym), int(n), int(ndata),
+                                  float(lr), float(beta1), float(beta2), float(eps), _ptr(loss)))
 
 
 def sclmlp_get_step(ctx) -> int:
@@ -101,13 +102,16 @@ def sclmlp_bad_rows(ctx) -> int:
 
 
 def init_params(seed: int) -> np.ndarray:
-    """He-normal weights, zero biases (float32), drawn on the host from a seeded generator."""
+    """Weights and biases uniform in +-1/sqrt(fan_in) (float32), drawn on the host
+    from a seeded generator.  (A He-normal start, 2.4x wider, fits the training
+    windows as well but generalises to unseen trajectories far worse.)"""
     rng = np.random.default_rng(seed)
     parts = []
     for i in range(len(WIDTHS) - 1):
         fan_in, fan_out = WIDTHS[i], WIDTHS[i + 1]
-        parts.append((rng.standard_normal((fan_out, fan_in)) * np.sqrt(2.0 / fan_in)).ravel())
-        parts.append(np.zeros(fan_out))
+        bound = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-bound, bound, fan_out * fan_in))
+        parts.append(rng.uniform(-bound, bound, fan_out))
     return np.concatenate(parts).astype(np.float32)
 
 
@@ -181,19 +185,20 @@ class Network:
         self._done(windows, out)
         return out
 
-    def gradients(self, windows, targets, index=None, n=None):
+    def gradients(self, windows, targets, index=None, sym=None, n=None):
         n = (index.shape[0] if index is not None else windows.shape[0]) if n is None else n
         self._sync_torch()
-        sclmlp_gradients(self.ctx, windows, targets, index, n, windows.shape[0], self.loss_buf)
-        self._done(windows, targets, index)
+        sclmlp_gradients(self.ctx, windows, targets, index, sym, n, windows.shape[0], self.loss_buf)
+        self._done(windows, targets, index, sym)
         return self.loss_buf
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         sclmlp_adam(self.ctx, lr, beta1, beta2, eps)
 
-    def train_step(self, windows, targets, index=None, n=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    def train_step(self, windows, targets, index=None, sym=None, n=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         n = (index.shape[0] if index is not None else windows.shape[0]) if n is None else n
         self._sync_torch()
-        sclmlp_train_step(self.ctx, windows, targets, index, n, windows.shape[0], lr, beta1, beta2, eps, self.loss_buf)
-        self._done(windows, targets, index)
+        sclmlp_train_step(self.ctx, windows, targets, index, sym, n, windows.shape[0], lr, beta1, beta2, eps,
+                          self.loss_buf)
+        self._done(windows, targets, index, sym)
         return self.loss_buf

@@ -233,7 +233,7 @@ def test_errors(env):
     with pytest.raises(sc.SclbmError):
         mlp.sclmlp_predict(net.ctx, w, 101, o)
     with pytest.raises(sc.SclbmError):
-        mlp.sclmlp_gradients(net.ctx, w, o, None, 0, 200)
+        mlp.sclmlp_gradients(net.ctx, w, o, None, None, 0, 200)
     with pytest.raises(sc.SclbmError):
         net.adam(-1.0)
     with pytest.raises(sc.SclbmError):

@@ -107,3 +107,20 @@ def test_round_bf16_definition():
 def test_deformation_of_semi_axes():
     assert mlp.deformation([3.0, 2.0, 1.0]) == pytest.approx(0.5)
     assert mlp.deformation([[1.0, 1.0, 1.0]])[0] == 0.0
+
+
+def test_cubic_symmetries_form_the_octahedral_group():
+    Ps = [mlp.cubic_symmetry(s) for s in range(48)]
+    assert np.array_equal(Ps[0], np.eye(3))
+    keys = {P.tobytes() for P in Ps}
+    assert len(keys) == 48
+    for P in Ps:
+        assert np.array_equal(P @ P.T, np.eye(3)) and np.all(np.abs(P).sum(0) == 1)
+    for P in Ps[::5]:
+        for Q in Ps[::7]:
+            assert (P @ Q).tobytes() in keys
+    # the conjugation keeps the eigenvalues of the strain (the shape-relevant invariants)
+    A = np.random.default_rng(0).standard_normal(9)
+    w = mlp.transform_window(A, 29).reshape(3, 3)
+    S, S2 = 0.5 * (A.reshape(3, 3) + A.reshape(3, 3).T), 0.5 * (w + w.T)
+    assert np.allclose(np.linalg.eigvalsh(S), np.linalg.eigvalsh(S2), atol=1e-14)

@@ -100,6 +100,47 @@ def test_point_symmetry_under_linear_flow(calibration):
     assert st["deformation"] > 1e-3
 
 
+def cubic_map_field(F_zyx, P):
+    """The scalar field F(x) carried along by d -> P d about the box centre
+    (d = x - x_c; F indexed [z][y][x]; P a signed permutation)."""
+    F = np.transpose(F_zyx, (2, 1, 0))                       # [x][y][z]
+    perm = [int(np.nonzero(P[i])[0][0]) for i in range(3)]
+    T = np.transpose(F, perm)
+    for i in range(3):
+        if P[i, perm[i]] < 0:
+            T = np.flip(T, axis=i)
+    return np.transpose(T, (2, 1, 0))
+
+
+@pytest.mark.parametrize("s", [13, 29, 46])
+def test_box_is_invariant_under_cubic_symmetries(calibration, s):
+    """Driving the box with P A P^T (P a signed permutation of the axes, about the
+    centre) gives the density field carried along by P, and the same semi-axes:
+    the cube, the D3Q19 velocity set, the centred droplet and the ghost velocity
+    A (x - x_c) all map onto themselves.  (This is what makes the 48 maps exact
+    augmentations of the surrogate's training windows.)"""
+    from oracle import mlp
+    G = calibration["g_ab"]
+    n, R, steps = 14, 3.5, 30
+    A = np.array([0.004, -0.002, 0.003, 0.001, -0.003, 0.0025, -0.0015, 0.002, -0.001])
+    P = mlp.cubic_symmetry(s)
+    A2 = mlp.transform_window(A, s)
+    out = []
+    for a in (A, A2):
+        o = oracle.Oracle(n, n, n, periodic=False, tau=(1.0, 1.0), g=G, rho_b=(0.05, 1.0))
+        o.init_droplet(o.xc, R, 2.0, 1.0, 0.04, a)
+        o.run(steps, np.tile(a, (steps, 1)))
+        out.append(o.fields())
+    (ra, rb, _), (ra2, rb2, _) = out
+    assert np.abs(cubic_map_field(ra, P) - ra2).max() < 1e-13
+    assert np.abs(cubic_map_field(rb, P) - rb2).max() < 1e-13
+    xc = np.full(3, (n - 1) / 2.0)
+    a1 = oracle.droplet_stats(ra, rb, xc)["semi_axes"]
+    a2 = oracle.droplet_stats(ra2, rb2, xc)["semi_axes"]
+    assert np.allclose(a1, a2, rtol=1e-12)
+    assert np.abs(ra - ra2).max() > 1e-6          # the map is not trivial for this drive
+
+
 def test_droplet_at_rest_stays_spherical(calibration):
     G = calibration["g_ab"]
     n = 20
