@@ -69,6 +69,11 @@ def _load():
         lib.orc_fields.argtypes = [P, dp, dp, dp, dp]
         lib.orc_totals.argtypes = [P, dp, dp]
         lib.orc_droplet_moments.argtypes = [I, I, I, dp, dp, dp, dp]
+        lib.orc_droplet_surface.argtypes = [I, I, I, dp, dp, dp]
+        lib.orc_droplet_mass.restype = D
+        lib.orc_droplet_mass.argtypes = [P]
+        lib.orc_reinject.restype = D
+        lib.orc_reinject.argtypes = [P, D]
         lib.orc_stencil.argtypes = [ip, dp]
         lib.orc_equilibrium.argtypes = [D, dp, dp]
         lib.orc_num_threads.restype = I
@@ -199,6 +204,15 @@ class Oracle:
         self.lib.orc_totals(self.h, _dp(m), _dp(p))
         return m, p
 
+    def droplet_mass(self) -> float:
+        """Sum of rho_A over the nodes with rho_A > rho_B."""
+        return float(self.lib.orc_droplet_mass(self.h))
+
+    def reinject(self, target: float) -> float:
+        """Scale the A populations of the droplet nodes so that the droplet mass
+        becomes ``target``; returns the mass before."""
+        return float(self.lib.orc_reinject(self.h, float(target)))
+
 
 def droplet_moments(rho_a: np.ndarray, rho_b: np.ndarray, center) -> np.ndarray:
     """{S0, S1(3), S2(xx,xy,xz,yy,yz,zz)} of phi = [rho_A > rho_B] about ``center``."""
@@ -210,6 +224,25 @@ def droplet_moments(rho_a: np.ndarray, rho_b: np.ndarray, center) -> np.ndarray:
     out = np.zeros(10)
     lib.orc_droplet_moments(nx, ny, nz, _dp(ra), _dp(rb), _dp(ctr), _dp(out))
     return out
+
+
+def droplet_surface(rho_a: np.ndarray, rho_b: np.ndarray):
+    """(area, volume) of the level set rho_A = rho_B and of the region rho_A > rho_B,
+    phi = rho_A - rho_B linear inside the six diagonal tetrahedra of every cell."""
+    lib = _load()
+    ra = np.ascontiguousarray(rho_a, dtype=np.float64)
+    rb = np.ascontiguousarray(rho_b, dtype=np.float64)
+    nz, ny, nx = ra.shape
+    out = np.zeros(2)
+    lib.orc_droplet_surface(nx, ny, nz, _dp(ra), _dp(rb), _dp(out))
+    return float(out[0]), float(out[1])
+
+
+def deformation_lbm(area: float, volume: float) -> float:
+    """D_LBM = sqrt(1 - Omega_0 / Omega) (Sec. 5 Eq. 17), Omega_0 = (36 pi V^2)^(1/3)
+    the area of the sphere of volume V."""
+    omega0 = (36.0 * np.pi * volume * volume) ** (1.0 / 3.0)
+    return float(np.sqrt(max(0.0, 1.0 - omega0 / area)))
 
 
 def droplet_stats_from_moments(mom: np.ndarray, center) -> dict:

@@ -408,3 +408,136 @@ void orc_droplet_moments(int nx, int ny, int nz, const double *rho_a, const doub
                 out[9] += d[2] * d[2];
             }
 }
+
+/* ---------------------------------------------- droplet surface and mass --- */
+
+/* Zero-level-set point on the edge from p (phi_p > 0) to q (phi_q <= 0). */
+static void edge_point(const double *p, const double *q, double fp, double fq, double *out) {
+    double t = fp / (fp - fq);
+    for (int a = 0; a < 3; a++) out[a] = p[a] + t * (q[a] - p[a]);
+}
+
+static double tri_area(const double *a, const double *b, const double *c) {
+    double u[3], v[3], w[3];
+    for (int k = 0; k < 3; k++) {
+        u[k] = b[k] - a[k];
+        v[k] = c[k] - a[k];
+    }
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+    return 0.5 * sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+}
+
+static double tet_volume(const double *a, const double *b, const double *c, const double *d) {
+    double u[3], v[3], w[3];
+    for (int k = 0; k < 3; k++) {
+        u[k] = b[k] - a[k];
+        v[k] = c[k] - a[k];
+        w[k] = d[k] - a[k];
+    }
+    double det = u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
+                 u[2] * (v[0] * w[1] - v[1] * w[0]);
+    return fabs(det) / 6.0;
+}
+
+/* Area of {phi = 0} and volume of {phi > 0} inside one tetrahedron (phi linear
+ * between the four vertex values). */
+static void tet_surface(double P[4][3], const double *phi, double *area, double *vol) {
+    int pos[4], neg[4], np = 0, nn = 0;
+    for (int i = 0; i < 4; i++) {
+        if (phi[i] > 0.0)
+            pos[np++] = i;
+        else
+            neg[nn++] = i;
+    }
+    if (np == 0) return;
+    if (np == 4) {
+        *vol += tet_volume(P[0], P[1], P[2], P[3]);
+        return;
+    }
+    if (np == 1) {
+        /* a corner tetrahedron cut off around the one positive vertex */
+        int a = pos[0];
+        double X[3][3];
+        for (int k = 0; k < 3; k++) edge_point(P[a], P[neg[k]], phi[a], phi[neg[k]], X[k]);
+        *area += tri_area(X[0], X[1], X[2]);
+        *vol += tet_volume(P[a], X[0], X[1], X[2]);
+    } else if (np == 3) {
+        /* the whole tetrahedron minus the corner around the one non-positive vertex */
+        int d = neg[0];
+        double X[3][3];
+        for (int k = 0; k < 3; k++) edge_point(P[pos[k]], P[d], phi[pos[k]], phi[d], X[k]);
+        *area += tri_area(X[0], X[1], X[2]);
+        *vol += tet_volume(P[0], P[1], P[2], P[3]) - tet_volume(P[d], X[0], X[1], X[2]);
+    } else {
+        /* two and two: a quadrilateral cut; the positive part is a prism with the
+         * triangles (a, Xac, Xad) and (b, Xbc, Xbd) as ends */
+        int a = pos[0], b = pos[1], c = neg[0], d = neg[1];
+        double Xac[3], Xad[3], Xbc[3], Xbd[3];
+        edge_point(P[a], P[c], phi[a], phi[c], Xac);
+        edge_point(P[a], P[d], phi[a], phi[d], Xad);
+        edge_point(P[b], P[c], phi[b], phi[c], Xbc);
+        edge_point(P[b], P[d], phi[b], phi[d], Xbd);
+        /* quadrilateral Xac - Xad - Xbd - Xbc (consecutive corners share a face) */
+        *area += tri_area(Xac, Xad, Xbd) + tri_area(Xac, Xbd, Xbc);
+        *vol += tet_volume(P[a], Xac, Xad, P[b]) + tet_volume(Xac, Xad, P[b], Xbd) + tet_volume(Xac, P[b], Xbc, Xbd);
+    }
+}
+
+/* Surface area of the droplet, the level set rho_A = rho_B, and the volume it
+ * encloses, for the D_LBM measure of Sec. 5 Eq. 17 (which needs the surface
+ * area of the deformed droplet and of the sphere of equal volume).  The paper
+ * does not say how the area is measured; here phi = rho_A - rho_B is taken as
+ * linear inside each of the six tetrahedra of every lattice cell (the cells
+ * split along their main diagonal), the zero set in each tetrahedron is a
+ * triangle or a planar quadrilateral, and the areas and the volumes of
+ * {phi > 0} are summed over all cells in node order.  out = {area, volume}. */
+void orc_droplet_surface(int nx, int ny, int nz, const double *rho_a, const double *rho_b, double *out) {
+    static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    double area = 0.0, vol = 0.0;
+    for (int z = 0; z + 1 < nz; z++)
+        for (int y = 0; y + 1 < ny; y++)
+            for (int x = 0; x + 1 < nx; x++) {
+                for (int t = 0; t < 6; t++) {
+                    double P[4][3], phi[4];
+                    int v[3] = {x, y, z};
+                    for (int i = 0; i < 4; i++) {
+                        if (i > 0) v[perms[t][i - 1]] += 1;
+                        size_t k = ((size_t)v[2] * ny + v[1]) * nx + v[0];
+                        P[i][0] = v[0];
+                        P[i][1] = v[1];
+                        P[i][2] = v[2];
+                        phi[i] = rho_a[k] - rho_b[k];
+                    }
+                    tet_surface(P, phi, &area, &vol);
+                }
+            }
+    out[0] = area;
+    out[1] = vol;
+}
+
+/* Droplet mass of component A: sum of rho_A over the nodes with rho_A > rho_B
+ * (node order). */
+double orc_droplet_mass(orc_state *s) {
+    phase_moments(s);
+    double m = 0.0;
+    for (size_t k = 0; k < s->n; k++)
+        if (s->rho[k] > s->rho[s->n + k]) m += s->rho[k];
+    return m;
+}
+
+/* Mass reinjection (Sec. 2: the boundary scheme does not conserve mass, and mass
+ * is reinjected into the droplet to keep its density fixed).  Reading: every A
+ * population at the droplet nodes (rho_A > rho_B) is multiplied by
+ * target / M, M the droplet mass of orc_droplet_mass, so that the droplet mass
+ * becomes target; the velocity of component A is unchanged.  Returns M. */
+double orc_reinject(orc_state *s, double target) {
+    double m = orc_droplet_mass(s);
+    double scale = target / m;
+    for (size_t k = 0; k < s->n; k++) {
+        if (!(s->rho[k] > s->rho[s->n + k])) continue;
+        for (int i = 0; i < Q; i++) fptr(s, s->f, 0, i)[k] *= scale;
+    }
+    return m;
+}
