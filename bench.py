@@ -12,6 +12,15 @@ Prints one JSON line with MLUPS (one update = both components at one node),
 the roofline of the step kernel (algorithmic bytes per launch over its average
 launch duration, from HIP events on the library's stream) and the FP64 CPU
 oracle timed on a bounded sample of the same box on the host cores.
+
+The same line carries the surrogate comparison ("surrogate"): the ensemble of
+64 boxes of 64^3 (R = 10, FP32, one OU drive each, 20000 lattice steps through
+the captured step loop, droplet moments every 50 steps) gives the lattice
+Boltzmann rate of shape samples and the training windows; the network is
+trained on 56 trajectories by the library's kernels and judged on the 8 held
+out, and one 8192-window inference batch is timed with HIP events.  Surrogate
+samples/s count the lattice Boltzmann replays of windows whose predicted D
+exceeds 0.5.
 """
 from __future__ import annotations
 
@@ -127,6 +136,57 @@ def precision_study(sc, nsteps: int):
     print(json.dumps(out))
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_study(train_steps: int = 10000, nsamp: int = 400, log=None):
+    """Ensemble data, training, held-out errors against the sphere and the
+    Maffettone-Minale model, inference throughput against the boxes' own."""
+    from paper_2112_09972_amd import surrogate as S
+    log = log or (lambda *a: None)
+    case = wl.case_c4(nsteps=(nsamp - 1) * STRIDE + 1)
+    run = S.generate(case, nsamp)
+    log("ensemble: %d boxes of %d^3, %d lattice steps, %.0f MLUPS" % (case.nbox, case.n, (nsamp - 1) * STRIDE,
+                                                                     run.mlups))
+    ws = S.make_windows(run)
+    tr, va = S.split_by_box(ws)
+    res = S.train(tr, steps=train_steps)
+    log("trained %d steps in %.1f s" % (res.steps, res.seconds))
+    val = S.predict_with_fallback(res.net, va.windows, radius=case.radius, n=case.n)
+    allw = S.predict_with_fallback(res.net, ws.windows, radius=case.radius, n=case.n)
+    mm = S.mm_shapes(run)
+    t_inf = S.inference_seconds(res.net, windows=np.resize(va.windows, (8192, va.windows.shape[1])))
+    lbm_rate = run.lattice_updates / run.seconds
+    f = float(allw.fallback.mean())
+    replay_lups = (S.WINDOW - 1) * STRIDE * case.n ** 3
+    per_sample = t_inf / 8192 + f * replay_lups / lbm_rate
+    flops = 2.0 * 8192 * (576 * 512 + 2 * 512 * 512 + 512 * 3)
+    achieved = flops / t_inf / 1e12
+    e = S.errors(val.axes, va.targets)
+    out = {
+        "workload": case.name, "boxes": case.nbox, "box": case.n, "radius": case.radius,
+        "lattice_steps": (nsamp - 1) * STRIDE, "ensemble_mlups": round(run.mlups, 1),
+        "ensemble_hbm_frac": round(run.mlups * 1e6 * 304 / (HBM_PEAK_GBS * 1e9), 4),
+        "ensemble_launch": {"tile_rows": run.launch[0], "zchunk": run.launch[1]},
+        "windows": {"train": int(len(tr.targets)), "held_out": int(len(va.targets)), "samples": 64, "stride": STRIDE},
+        "train": {"steps": res.steps, "batch": 256, "seconds": round(res.seconds, 2), "augment": "48 cubic maps"},
+        "lbm_samples_per_s": round(run.lbm_samples_per_s, 1),
+        "inference_batch": 8192, "inference_ms": round(t_inf * 1e3, 4),
+        "fallback_threshold_D": 0.5, "fallback_fraction": f,
+        "samples_per_s": round(1.0 / per_sample, 1),
+        "speedup_vs_lbm": round(1.0 / per_sample / run.lbm_samples_per_s, 1),
+        "semi_axis_rel_err": {k: round(v, 5) for k, v in e.items()},
+        "within_5pct": bool(e["max"] <= 0.05),
+        "baselines": {"sphere": {k: round(v, 5) for k, v in S.errors(np.ones_like(va.targets), va.targets).items()},
+                      "maffettone_minale": {k: round(v, 5) for k, v in S.errors(mm[va.box, va.k], va.targets).items()}},
+        "roofline": {"bound": "mfma", "kernel": "inference batch (3 k_gemm_nt + k_out)",
+                     "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "flops_per_batch": flops},
+    }
+    res.net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +198,8 @@ def main():
     ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
                     help="c2: the headline 128^3 FP32 box (default); c3: the 256^3 precision study")
     ap.add_argument("--c3-steps", type=int, default=10000)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate comparison")
+    ap.add_argument("--surrogate-train-steps", type=int, default=10000)
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -207,7 +269,7 @@ def main():
     achieved = bytes_per_lup * nodes / (step_ms * 1e-3) / 1e9
     ty, zc = lat.get_launch()
     out = {
-        "metric": "MLUPS & % HBM peak (2-comp LBM)",
+        "metric": "MLUPS & % HBM peak (2-comp LBM); surrogate vs LBM samples/sec at <=5% err",
         "value": round(mlups, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -229,8 +291,16 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(case.name),
                      "bytes_per_launch": bytes_per_lup * nodes, "avg_launch_ms": round(step_ms, 5)},
     }
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    log("timed %d x %d lattice steps: %.1f MLUPS" % (K, STRIDE, mlups))
+    lat.close()
+    del lat, moments
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+        log("cpu baseline: %s" % out["cpu_baseline"]["value"])
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_study(args.surrogate_train_steps, log=log)
     print(json.dumps(out))
 
 

@@ -186,6 +186,34 @@ sclbm_status sclbm_droplet(sclbm_ctx *ctx, int32_t box, sclbm_droplet_stats *out
  * averages over the box's nodes, u as in sclbm_fields.  Synchronises. */
 sclbm_status sclbm_velocity_error(sclbm_ctx *ctx, int32_t box, const double A[9], double *e0);
 
+/* Droplet surface, for the deformation measure D_LBM = sqrt(1 - Omega_0 / Omega)
+ * of Sec. 5 Eq. 17 (Omega the droplet's surface area, Omega_0 that of the sphere
+ * of equal volume).  For every box: the area of the level set rho_A = rho_B
+ * and the volume of rho_A > rho_B, with phi = rho_A - rho_B taken linear inside
+ * the six tetrahedra of every lattice cell (each cell split along its main
+ * diagonal; the paper does not say how it measures the area).  dev_out:
+ * [nbox][2] = {area, volume}, FP64 sums in a fixed order.  Enqueued. */
+sclbm_status sclbm_droplet_surface_all(sclbm_ctx *ctx, double *dev_out);
+
+/* D_LBM from an area and a volume (host arithmetic; area > 0, volume >= 0);
+ * Omega_0 = (36 pi V^2)^(1/3).  0 when the area does not exceed Omega_0. */
+sclbm_status sclbm_deformation_lbm(double area, double volume, double *d_lbm);
+
+/* Droplet mass of every box: the sum of rho_A over the nodes with
+ * rho_A > rho_B.  dev_out: [nbox] FP64.  Enqueued. */
+sclbm_status sclbm_droplet_mass_all(sclbm_ctx *ctx, double *dev_out);
+
+/* Mass reinjection (Sec. 2: the ghost-node boundary does not conserve mass,
+ * and mass is put back into the droplet so that its density stays fixed).
+ * For box `box` (or every box, box = -1): measure the droplet mass M as in
+ * sclbm_droplet_mass_all and multiply component A at every droplet node by
+ * target / M — every population in the FP64/FP32 formats, the node's reference
+ * density in the deviation formats (rounded to FP16 there).  Component A's
+ * velocity is unchanged.  target_mass: host, one value per selected box (> 0).
+ * A scale above 1 reaches the target exactly; below 1, interface nodes may
+ * leave the droplet and the mass lands slightly under it.  Synchronises. */
+sclbm_status sclbm_reinject(sclbm_ctx *ctx, int32_t box, const double *target_mass);
+
 /* Checkpoint: bytes needed, save the state (populations of every box, time)
  * into host memory, restore it.  Save synchronises; load is bitwise exact. */
 sclbm_status sclbm_state_bytes(const sclbm_ctx *ctx, size_t *bytes);

@@ -53,6 +53,7 @@ EXPORTS = [
     "sclbm_droplet_moments", "sclbm_droplet_from_moments", "sclbm_droplet", "sclbm_velocity_error",
     "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch",
     "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune", "sclbm_droplet_moments_all", "sclbm_mm_integrate",
+    "sclbm_droplet_surface_all", "sclbm_deformation_lbm", "sclbm_droplet_mass_all", "sclbm_reinject",
     # droplet-shape surrogate (sclmlp.h)
     "sclmlp_workspace_bytes", "sclmlp_create", "sclmlp_destroy", "sclmlp_set_params", "sclmlp_get_params",
     "sclmlp_get_grads", "sclmlp_set_normalization", "sclmlp_predict", "sclmlp_gradients", "sclmlp_adam",
@@ -84,6 +85,10 @@ def _load_library():
         "sclbm_totals": [P, I32, dp, dp],
         "sclbm_droplet_moments": [P, I32, P],
         "sclbm_droplet_moments_all": [P, P],
+        "sclbm_droplet_surface_all": [P, P],
+        "sclbm_deformation_lbm": [D, D, dp],
+        "sclbm_droplet_mass_all": [P, P],
+        "sclbm_reinject": [P, I32, dp],
         "sclbm_mm_integrate": [P, I64, I64, D, D, I32, I32, P, P, P],
         "sclbm_droplet_from_moments": [dp, dp, I64, ctypes.POINTER(sclbm_droplet_stats)],
         "sclbm_droplet": [P, I32, ctypes.POINTER(sclbm_droplet_stats)],
@@ -225,6 +230,25 @@ def sclbm_droplet_moments(ctx, box, dev_out_ptr):
 
 def sclbm_droplet_moments_all(ctx, dev_out_ptr):
     _check(_lib.sclbm_droplet_moments_all(ctx, ctypes.c_void_p(dev_out_ptr)))
+
+
+def sclbm_droplet_surface_all(ctx, dev_out_ptr):
+    _check(_lib.sclbm_droplet_surface_all(ctx, ctypes.c_void_p(dev_out_ptr)))
+
+
+def sclbm_deformation_lbm(area, volume) -> float:
+    d = ctypes.c_double()
+    _check(_lib.sclbm_deformation_lbm(float(area), float(volume), ctypes.byref(d)))
+    return d.value
+
+
+def sclbm_droplet_mass_all(ctx, dev_out_ptr):
+    _check(_lib.sclbm_droplet_mass_all(ctx, ctypes.c_void_p(dev_out_ptr)))
+
+
+def sclbm_reinject(ctx, box, target_mass):
+    t = np.ascontiguousarray(np.atleast_1d(np.asarray(target_mass, dtype=np.float64)))
+    _check(_lib.sclbm_reinject(ctx, int(box), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
 
 def sclbm_droplet_from_moments(moments, center, step=0) -> dict:
@@ -431,6 +455,32 @@ class Lattice:
         """Enqueue the 10 indicator moments of every box into the device tensor out[nbox][10]."""
         assert out.shape == (self.nbox, 10) and out.is_contiguous()
         sclbm_droplet_moments_all(self.ctx, out.data_ptr())
+
+    def droplet_surface_all(self, out):
+        """Enqueue {area, volume} of every box's droplet into the device tensor out[nbox][2]."""
+        assert out.shape == (self.nbox, 2) and out.is_contiguous()
+        sclbm_droplet_surface_all(self.ctx, out.data_ptr())
+
+    def droplet_surface(self, box=0):
+        """(area, volume, D_LBM) of one box's droplet (synchronises)."""
+        out = self.torch.empty((self.nbox, 2), dtype=self.torch.float64, device=self.device)
+        self._sync_torch()
+        self.droplet_surface_all(out)
+        self.stream.synchronize()
+        area, vol = (float(v) for v in out[box].cpu())
+        return area, vol, sclbm_deformation_lbm(area, vol)
+
+    def droplet_mass(self):
+        """Droplet mass of every box (numpy, synchronises)."""
+        out = self.torch.empty(self.nbox, dtype=self.torch.float64, device=self.device)
+        self._sync_torch()
+        sclbm_droplet_mass_all(self.ctx, out.data_ptr())
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def reinject(self, target_mass, box=-1):
+        """Scale component A in the droplet(s) so that the droplet mass becomes the target."""
+        sclbm_reinject(self.ctx, box, target_mass)
 
     def velocity_error(self, A, box=0) -> float:
         return sclbm_velocity_error(self.ctx, box, A)

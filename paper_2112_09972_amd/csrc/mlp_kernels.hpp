@@ -42,12 +42,18 @@ constexpr int NPARAM = OFF_B4 + NOUT;
 static_assert(NPARAM == 822275, "parameter count");
 
 // ---------------------------------------------------------------------------------------------
-// GEMM: C = A B^T with an epilogue.  A [M][K] (row stride lda), B [N][K] (ldb), K % 64 == 0.
+// GEMM: C = A B^T with an epilogue.  A [M][K] (row stride lda), B [N][K] (ldb), K % 8 == 0.
+// K is staged through LDS BK columns at a time (k beyond K reads as zero); deep stages keep
+// many loads in flight per workgroup, which the short contractions here need to hide HBM latency.
 enum Epi { EPI_RELU = 0, EPI_MASK = 1, EPI_F32 = 2 };
 
 struct GemmArgs {
     const bf16 *A, *B;
     int M, N, K, lda, ldb;
+    // AF32 form: A is FP32 (Af, row stride lda), normalised on the fly as (a - ashift[k]) * ascale[k]
+    // and rounded to BF16 while staged; rows >= arows read as zero.
+    const float *Af, *ashift, *ascale;
+    int arows;
     const float *bias;   // EPI_RELU: per column n
     const bf16 *mask;    // EPI_MASK: element (m, n) kept where mask > 0 (row stride ldmask)
     int ldmask;
@@ -59,15 +65,21 @@ struct GemmArgs {
 
 __device__ __forceinline__ uint4 ld16(const bf16 *p) { return *reinterpret_cast<const uint4 *>(p); }
 
-template <int BM, int BN, int EPI>
+template <int BM, int BN, int BK, int EPI, bool AF32 = false>
 __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
-    constexpr int BK = 64, LDK = BK + 8;   // 16-byte pad per LDS row spreads the fragment reads over banks
+    constexpr int LDK = BK + 8;            // 16-byte pad per LDS row spreads the fragment reads over banks
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int FM = WM / 32, FN = WN / 32;
-    constexpr int CA = BM * 8 / 256, CB = BN * 8 / 256;
+    constexpr int RC = BK / 8;             // 16-byte chunks per tile row
+    constexpr int CA = BM * RC / 256, CB = BN * RC / 256;
+    static_assert(BK % 64 == 0 && (BM * RC) % 256 == 0 && (BN * RC) % 256 == 0, "tile");
     static_assert(FM >= 1 && FN >= 1 && CA >= 1 && CB >= 1, "tile");
-    __shared__ __attribute__((aligned(16))) bf16 As[BM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * LDK];
+    // one LDS buffer: the A and B stages during the contraction, then the BF16 output tile
+    constexpr int LDC = BN + 8;
+    constexpr int SMEM = (BM + BN) * LDK > BM * LDC ? (BM + BN) * LDK : BM * LDC;
+    __shared__ __attribute__((aligned(16))) bf16 smem[SMEM];
+    bf16 *const As = smem;
+    bf16 *const Bs = smem + BM * LDK;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -79,28 +91,58 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
     const int m0 = (lin / ntn) * BM, n0 = (lin % ntn) * BN;
 
     uint4 ra[CA], rb[CB];
+    float4 fa[CA][2];  // AF32: raw FP32 A chunks, normalised and converted when staged
     auto gload = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < CA; ++i) {
-            const int c = tid + 256 * i, r = c >> 3, kc = (c & 7) * 8;
-            ra[i] = (m0 + r < g.M) ? ld16(g.A + (size_t)(m0 + r) * g.lda + k0 + kc) : make_uint4(0, 0, 0, 0);
+            const int c = tid + 256 * i, r = c / RC, kc = (c % RC) * 8;
+            if (AF32) {
+                const bool live = m0 + r < g.arows && k0 + kc < g.K;
+                const float4 *src =
+                    reinterpret_cast<const float4 *>(g.Af + (live ? (size_t)(m0 + r) * g.lda + k0 + kc : 0));
+                fa[i][0] = live ? src[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                fa[i][1] = live ? src[1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            } else {
+                ra[i] = (m0 + r < g.M && k0 + kc < g.K) ? ld16(g.A + (size_t)(m0 + r) * g.lda + k0 + kc)
+                                                         : make_uint4(0, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
-            const int c = tid + 256 * i, r = c >> 3, kc = (c & 7) * 8;
-            rb[i] = (n0 + r < g.N) ? ld16(g.B + (size_t)(n0 + r) * g.ldb + k0 + kc) : make_uint4(0, 0, 0, 0);
+            const int c = tid + 256 * i, r = c / RC, kc = (c % RC) * 8;
+            rb[i] = (n0 + r < g.N && k0 + kc < g.K) ? ld16(g.B + (size_t)(n0 + r) * g.ldb + k0 + kc)
+                                                     : make_uint4(0, 0, 0, 0);
         }
     };
-    auto sstore = [&]() {
+    auto sstore = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < CA; ++i) {
-            const int c = tid + 256 * i;
-            *reinterpret_cast<uint4 *>(As + (c >> 3) * LDK + (c & 7) * 8) = ra[i];
+            const int c = tid + 256 * i, r = c / RC, kc = (c % RC) * 8;
+            if (AF32) {
+                const int kq = k0 + kc < g.K ? k0 + kc : 0;
+                const float4 sa = *reinterpret_cast<const float4 *>(g.ashift + kq);
+                const float4 sb = *reinterpret_cast<const float4 *>(g.ashift + kq + 4);
+                const float4 ca = *reinterpret_cast<const float4 *>(g.ascale + kq);
+                const float4 cb = *reinterpret_cast<const float4 *>(g.ascale + kq + 4);
+                bf16x8 h;
+                h[0] = (bf16)((fa[i][0].x - sa.x) * ca.x);
+                h[1] = (bf16)((fa[i][0].y - sa.y) * ca.y);
+                h[2] = (bf16)((fa[i][0].z - sa.z) * ca.z);
+                h[3] = (bf16)((fa[i][0].w - sa.w) * ca.w);
+                h[4] = (bf16)((fa[i][1].x - sb.x) * cb.x);
+                h[5] = (bf16)((fa[i][1].y - sb.y) * cb.y);
+                h[6] = (bf16)((fa[i][1].z - sb.z) * cb.z);
+                h[7] = (bf16)((fa[i][1].w - sb.w) * cb.w);
+                if (m0 + r >= g.arows || k0 + kc >= g.K) h = bf16x8{};
+                *reinterpret_cast<bf16x8 *>(As + r * LDK + kc) = h;
+            } else {
+                *reinterpret_cast<uint4 *>(As + r * LDK + kc) = ra[i];
+            }
         }
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
             const int c = tid + 256 * i;
-            *reinterpret_cast<uint4 *>(Bs + (c >> 3) * LDK + (c & 7) * 8) = rb[i];
+            *reinterpret_cast<uint4 *>(Bs + (c / RC) * LDK + (c % RC) * 8) = rb[i];
         }
     };
 
@@ -112,9 +154,9 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
-    const int nk = g.K / BK;
+    const int nk = (g.K + BK - 1) / BK;
     gload(0);
-    sstore();
+    sstore(0);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         if (kt + 1 < nk) gload((kt + 1) * BK);
@@ -136,57 +178,84 @@ __global__ __launch_bounds__(256) void k_gemm_nt(GemmArgs g) {
         }
         if (kt + 1 < nk) {
             __syncthreads();
-            sstore();
+            sstore((kt + 1) * BK);
             __syncthreads();
         }
     }
 
     // accumulator element 4q + j of a 32x32 fragment sits at row 8q + 4 (lane / 32) + j, column lane % 32
+    if (EPI == EPI_F32) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int col = n0 + wn * WN + j * 32 + (lane & 31);
+                if (col >= g.N) continue;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row0 = m0 + wm * WM + i * 32 + 8 * q + 4 * (lane >> 5);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (row0 + e < g.M)
+                            static_cast<float *>(g.C)[(size_t)(row0 + e) * g.ldc + col] = acc[i][j][4 * q + e];
+                }
+            }
+        return;
+    }
+    // BF16 outputs: bias + ReLU or the ReLU mask, into an LDS tile, then 16-byte rows to memory
+    __syncthreads();  // every wave is done with the A and B stages
+    bf16 *const Cs = smem;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int col = n0 + wn * WN + j * 32 + (lane & 31);
-            if (col >= g.N) continue;
-            float bias = 0.0f;
-            if (EPI == EPI_RELU) bias = g.bias[col];
+            const int cl = wn * WN + j * 32 + (lane & 31), col = n0 + cl;
+            const float bias = (EPI == EPI_RELU && col < g.N) ? g.bias[col] : 0.0f;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row0 = m0 + wm * WM + i * 32 + 8 * q + 4 * (lane >> 5);
-                float v[4];
+                const int rl = wm * WM + i * 32 + 8 * q + 4 * (lane >> 5);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    v[e] = acc[i][j][4 * q + e];
-                    if (EPI == EPI_RELU) v[e] = fmaxf(v[e] + bias, 0.0f);
-                    if (EPI == EPI_MASK && row0 + e < g.M)
-                        v[e] = (float)g.mask[(size_t)(row0 + e) * g.ldmask + col] > 0.0f ? v[e] : 0.0f;
-                }
-                if (EPI == EPI_F32) {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (row0 + e < g.M) static_cast<float *>(g.C)[(size_t)(row0 + e) * g.ldc + col] = v[e];
-                } else {
-                    bf16 h[4];
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) h[e] = (bf16)v[e];
-                    if (g.C) {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (row0 + e < g.M) static_cast<bf16 *>(g.C)[(size_t)(row0 + e) * g.ldc + col] = h[e];
+                    float v = acc[i][j][4 * q + e];
+                    if (EPI == EPI_RELU) v = fmaxf(v + bias, 0.0f);
+                    if (EPI == EPI_MASK) {
+                        const int row = m0 + rl + e;
+                        v = (row < g.M && col < g.N && (float)g.mask[(size_t)row * g.ldmask + col] > 0.0f) ? v : 0.0f;
                     }
-                    if (g.CT) {
-                        bf16 *dst = g.CT + (size_t)col * g.ldct + row0;
-                        if (row0 + 3 < g.M) {
-                            bf16x4 p4 = {h[0], h[1], h[2], h[3]};
-                            *reinterpret_cast<bf16x4 *>(dst) = p4;
-                        } else {
-                            for (int e = 0; e < 4; ++e)
-                                if (row0 + e < g.M) dst[e] = h[e];
-                        }
-                    }
+                    Cs[(rl + e) * LDC + cl] = (bf16)v;
                 }
             }
         }
+    __syncthreads();
+    if (g.C) {
+        bf16 *C = static_cast<bf16 *>(g.C);
+        for (int c = tid; c < BM * BN / 8; c += 256) {
+            const int r = c / (BN / 8), cc = (c % (BN / 8)) * 8;
+            const int row = m0 + r, col = n0 + cc;
+            if (row >= g.M) continue;
+            if (col + 8 <= g.N) {
+                *reinterpret_cast<uint4 *>(C + (size_t)row * g.ldc + col) = *reinterpret_cast<const uint4 *>(Cs + r * LDC + cc);
+            } else {
+                for (int e = 0; e < 8 && col + e < g.N; ++e) C[(size_t)row * g.ldc + col + e] = Cs[r * LDC + cc + e];
+            }
+        }
+    }
+    if (g.CT) {
+        for (int c = tid; c < BM * BN / 8; c += 256) {
+            const int r = c / (BM / 8), mm = (c % (BM / 8)) * 8;  // r: column of the tile, mm: first row
+            const int col = n0 + r, row0 = m0 + mm;
+            if (col >= g.N) continue;
+            bf16x8 h;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) h[e] = Cs[(mm + e) * LDC + r];
+            bf16 *dst = g.CT + (size_t)col * g.ldct + row0;
+            if (row0 + 8 <= g.M) {
+                *reinterpret_cast<bf16x8 *>(dst) = h;
+            } else {
+                for (int e = 0; e < 8 && row0 + e < g.M; ++e) dst[e] = h[e];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -247,7 +316,9 @@ __global__ __launch_bounds__(256) void k_prep(const float *win, const int32_t *i
 // ---------------------------------------------------------------------------------------------
 // Output layer (3 units, no activation): one wave per row, each lane 8 of the 512 inputs.
 // PREDICT: writes de-normalised semi-axes for rows < n.  Training: writes dY = 2 (y - t) / (3 n)
-// (zero on padding rows) and per-block sums of (y - t)^2 and of dY.  64 rows per block.
+// (zero on padding rows) and per-block sums of (y - t)^2 and of dY.  OUT_ROWS rows per block
+// (two per wave: few dependent loads per wave, many blocks in flight).
+constexpr int OUT_ROWS = 8;
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -270,8 +341,8 @@ __global__ __launch_bounds__(256) void k_out(const bf16 *H, const bf16 *W4, cons
     }
     double loss = 0.0, db[NOUT] = {0.0, 0.0, 0.0};
     const float inv = n > 0 ? 2.0f / (3.0f * (float)n) : 0.0f;
-    for (int r = 0; r < 16; ++r) {
-        const int m = blockIdx.x * 64 + wave * 16 + r;
+    for (int r = 0; r < OUT_ROWS / 4; ++r) {
+        const int m = blockIdx.x * OUT_ROWS + wave * (OUT_ROWS / 4) + r;
         const bf16x8 h = *reinterpret_cast<const bf16x8 *>(H + (size_t)m * NHID + lane * 8);
         float s[NOUT] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -320,16 +391,27 @@ __global__ __launch_bounds__(256) void k_out(const bf16 *H, const bf16 *W4, cons
     }
 }
 
-// Fixed-order sum of the per-block partials: loss = sum (y - t)^2 / (3 n), db4 = sum dY.
-__global__ void k_loss_final(const double *partial, int nblocks, int n, double *loss, float *db4) {
-    const int j = threadIdx.x;
-    if (j >= 4) return;
-    double t = 0.0;
-    for (int b = 0; b < nblocks; ++b) t += partial[b * 4 + j];
-    if (j == 0) {
-        if (loss) *loss = n > 0 ? t / (3.0 * (double)n) : 0.0;
-    } else {
-        db4[j - 1] = (float)t;
+// Sum of the per-block partials in a fixed order (thread t takes blocks t, t + 256, ...; then a
+// fixed tree): loss = sum (y - t)^2 / (3 n), db4 = sum dY.  One block of 256 threads.
+__global__ __launch_bounds__(256) void k_loss_final(const double *partial, int nblocks, int n, double *loss,
+                                                    float *db4) {
+    __shared__ double red[256][4];
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[j] += partial[b * 4 + j];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[threadIdx.x][j] = t[j];
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[threadIdx.x][j] += red[threadIdx.x + h][j];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (loss) *loss = n > 0 ? red[0][0] / (3.0 * (double)n) : 0.0;
+        for (int j = 0; j < NOUT; ++j) db4[j] = (float)red[0][1 + j];
     }
 }
 

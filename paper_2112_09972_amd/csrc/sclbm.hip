@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "analysis_kernels.hpp"
 #include "aux_kernels.hpp"
 #include "lattice.hpp"
 #include "mm_kernel.hpp"
@@ -50,7 +51,7 @@ constexpr size_t kAlign = 256;
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t f0, f1, ref0, ref1, atab, first, clock, partial, result, diag, total;
+    size_t f0, f1, ref0, ref1, atab, first, clock, partial, result, mass, diag, total;
     size_t fbytes;    // populations of every box, one buffer
     size_t refbytes;  // per-node FP16 reference densities (deviation formats), one buffer
 };
@@ -102,6 +103,7 @@ Layout make_layout(const sclbm_config *c) {
     L.clock = off; off += round_up(2 * 8);
     L.partial = off; off += round_up(std::max<size_t>(size_t(NRED_BLOCKS), size_t(c->nbox) * stats_blocks(c)) * NSTAT * 8);
     L.result = off; off += round_up(size_t(c->nbox) * NSTAT * 8);
+    L.mass = off; off += round_up(size_t(c->nbox) * 2 * 8);  // droplet mass now, reinjection target
     L.diag = off; off += round_up(5 * N * 8);
     L.total = off;
     return L;
@@ -134,6 +136,8 @@ struct sclbm_ctx {
     size_t box_bytes() const { return size_t(2) * Q * size_t(N) * elem_bytes(cfg.prec); }
     double *partial() { return reinterpret_cast<double *>(ws + lay.partial); }
     double *result() { return reinterpret_cast<double *>(ws + lay.result); }
+    double *mass_now() { return reinterpret_cast<double *>(ws + lay.mass); }
+    double *mass_target() { return reinterpret_cast<double *>(ws + lay.mass) + cfg.nbox; }
     double *diag() { return reinterpret_cast<double *>(ws + lay.diag); }
     int64_t *clock() { return reinterpret_cast<int64_t *>(ws + lay.clock); }
 };
@@ -306,6 +310,23 @@ sclbm_status launch_stats(sclbm_ctx *c, int32_t b0, int32_t nb) {
     });
     if (e != hipSuccess) return fail(SCLBM_EHIP, "stats kernel: %s", hipGetErrorString(e));
     hipLaunchKernelGGL((k_final<NSTAT>), dim3(nb), dim3(NRED_THREADS), 0, c->stream, c->partial(), bpb, c->result());
+    HIP_LAUNCHED();
+    return SCLBM_OK;
+}
+
+// Droplet mass (sum of rho_A where rho_A > rho_B) of boxes [b0, b0 + nb) into c->mass_now() + b0.
+sclbm_status launch_drop_mass(sclbm_ctx *c, int32_t b0, int32_t nb) {
+    const int bpb = int(stats_blocks(&c->cfg));
+    hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        using S = typename Prec<P>::S;
+        const S *f = reinterpret_cast<const S *>(c->fbuf(c->par));
+        hipLaunchKernelGGL((k_drop_mass<P>), dim3(bpb, nb), dim3(NRED_THREADS), 0, c->stream, f, c->refbuf(c->par),
+                           c->geom, b0, c->partial());
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return fail(SCLBM_EHIP, "droplet mass kernel: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL((k_final<1>), dim3(nb), dim3(NRED_THREADS), 0, c->stream, c->partial(), bpb, c->mass_now() + b0);
     HIP_LAUNCHED();
     return SCLBM_OK;
 }
@@ -708,6 +729,73 @@ sclbm_status sclbm_droplet(sclbm_ctx *c, int32_t box, sclbm_droplet_stats *out) 
     HIP_TRY(hipMemcpyAsync(r, c->result(), sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return sclbm_droplet_from_moments(r + 5, c->geom.xc, c->n, out);
+}
+
+sclbm_status sclbm_droplet_surface_all(sclbm_ctx *c, double *dev_out) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!dev_out) return fail(SCLBM_EINVAL, "null output");
+    const int ntx = (c->cfg.nx - 1 + SURF_T - 1) / SURF_T, nty = (c->cfg.ny - 1 + SURF_T - 1) / SURF_T;
+    const int ntiles = ntx * nty;
+    // at most 8 stats blocks' worth of partials per box (2 values each instead of 16)
+    const int nblk = std::min<int>(ntiles, int(8 * stats_blocks(&c->cfg)));
+    hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        using S = typename Prec<P>::S;
+        const S *f = reinterpret_cast<const S *>(c->fbuf(c->par));
+        hipLaunchKernelGGL((k_surface<P>), dim3(nblk, c->cfg.nbox), dim3(NRED_THREADS), 0, c->stream, f,
+                           c->refbuf(c->par), c->geom, 0, ntx, ntiles, c->partial());
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return fail(SCLBM_EHIP, "surface kernel: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL((k_final<2>), dim3(c->cfg.nbox), dim3(NRED_THREADS), 0, c->stream, c->partial(), nblk, dev_out);
+    HIP_LAUNCHED();
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_deformation_lbm(double area, double volume, double *d_lbm) {
+    if (!d_lbm) return fail(SCLBM_EINVAL, "null output");
+    if (!(area > 0.0) || !(volume >= 0.0)) return fail(SCLBM_EINVAL, "area must be positive, volume non-negative");
+    const double omega0 = std::cbrt(36.0 * M_PI * volume * volume);
+    *d_lbm = std::sqrt(std::max(0.0, 1.0 - omega0 / area));
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_droplet_mass_all(sclbm_ctx *c, double *dev_out) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!dev_out) return fail(SCLBM_EINVAL, "null output");
+    if ((st = launch_drop_mass(c, 0, c->cfg.nbox))) return st;
+    HIP_TRY(hipMemcpyAsync(dev_out, c->mass_now(), size_t(c->cfg.nbox) * sizeof(double), hipMemcpyDeviceToDevice,
+                           c->stream));
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_reinject(sclbm_ctx *c, int32_t box, const double *target_mass) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, true))) return st;
+    if (!target_mass) return fail(SCLBM_EINVAL, "null target");
+    const int32_t b0 = box < 0 ? 0 : box, nb = box < 0 ? c->cfg.nbox : 1;
+    for (int32_t i = 0; i < nb; ++i)
+        if (!(target_mass[i] > 0.0) || !std::isfinite(target_mass[i]))
+            return fail(SCLBM_EINVAL, "target mass %d must be positive and finite", i);
+    HIP_TRY(hipMemcpyAsync(c->mass_target() + b0, target_mass, size_t(nb) * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+    if ((st = launch_drop_mass(c, b0, nb))) return st;
+    hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        using S = typename Prec<P>::S;
+        S *f = reinterpret_cast<S *>(c->fbuf(c->par));
+        const unsigned blocks = std::min<unsigned>(grid1d(c->N, 256), 2048u);
+        hipLaunchKernelGGL((k_reinject<P>), dim3(blocks, nb), dim3(256), 0, c->stream, f, c->refbuf(c->par), c->geom,
+                           b0, c->mass_now(), c->mass_target());
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return fail(SCLBM_EHIP, "reinjection kernel: %s", hipGetErrorString(e));
+    // the host copy of the target must outlive the transfer
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SCLBM_OK;
 }
 
 sclbm_status sclbm_velocity_error(sclbm_ctx *c, int32_t box, const double A[9], double *e0) {

@@ -86,7 +86,7 @@ Layout make_layout(int64_t mmax) {
     L.dzat = take(sizeof(bf16) * m * NHID);
     L.dzbt = take(sizeof(bf16) * m * NHID);
     L.dy = take(sizeof(float) * m * NOUT);
-    L.partial = take(sizeof(double) * 4 * (m / 64));
+    L.partial = take(sizeof(double) * 4 * (m / OUT_ROWS));
     L.loss = take(sizeof(double));
     L.bad = take(sizeof(unsigned));
     L.total = off;
@@ -121,18 +121,23 @@ struct sclmlp_ctx {
 
 namespace {
 
-// C = A B^T with the epilogue EPI; picks the 128 x 128 tile when it still gives at
-// least one workgroup per compute unit, else 64 x 64.
-template <int EPI>
+// C = A B^T with the epilogue EPI.  Tiles of 64 x 128 (two waves down, two across, each
+// 32 x 64) when the product has at least 1024 rows, else 64 x 64; K staged 64 columns at a
+// time (measured on the 8192 x 512 x 576 and x 512 products: deeper stages and 128 x 128
+// tiles were slower).
+template <int EPI, bool AF32 = false>
 sclbm_status gemm(const sclmlp_ctx *c, const GemmArgs &g) {
-    if (g.K % 64 != 0 || g.M <= 0 || g.N <= 0) return fail(SCLBM_EINVAL, "gemm shape %d x %d x %d", g.M, g.N, g.K);
-    const long big = (long)((g.M + 127) / 128) * ((g.N + 127) / 128);
-    if (big >= 256) {
-        dim3 grid((g.N + 127) / 128, (g.M + 127) / 128);
-        k_gemm_nt<128, 128, EPI><<<grid, 256, 0, c->stream>>>(g);
+    if (g.K % 8 != 0 || g.K <= 0 || g.M <= 0 || g.N <= 0)
+        return fail(SCLBM_EINVAL, "gemm shape %d x %d x %d", g.M, g.N, g.K);
+    // 16-byte loads and stores: row strides in whole 8-element groups
+    if (g.lda % 8 || g.ldb % 8 || (EPI != EPI_F32 && ((g.C && g.ldc % 8) || (g.CT && g.ldct % 8))))
+        return fail(SCLBM_EINVAL, "gemm row strides must be multiples of 8");
+    if (g.M >= 1024) {
+        dim3 grid((g.N + 127) / 128, (g.M + 63) / 64);
+        k_gemm_nt<64, 128, 64, EPI, AF32><<<grid, 256, 0, c->stream>>>(g);
     } else {
         dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
-        k_gemm_nt<64, 64, EPI><<<grid, 256, 0, c->stream>>>(g);
+        k_gemm_nt<64, 64, 64, EPI, AF32><<<grid, 256, 0, c->stream>>>(g);
     }
     HIP_LAUNCHED();
     return SCLBM_OK;
@@ -151,7 +156,10 @@ GemmArgs gargs(const bf16 *A, int lda, const bf16 *B, int ldb, int M, int N, int
 }
 
 // The three hidden layers (bias + ReLU); with `transposed` also the [unit][row] copies.
-sclbm_status hidden_forward(const sclmlp_ctx *c, int Mp, bool transposed) {
+// With `windows` (inference) the first layer reads the n FP32 windows directly and normalises
+// them while staging; otherwise it reads the BF16 inputs the preparation kernel wrote.
+sclbm_status hidden_forward(const sclmlp_ctx *c, int Mp, bool transposed, const float *windows = nullptr,
+                            int n = 0) {
     const float *P = c->P();
     const int boff[3] = {OFF_B1, OFF_B2, OFF_B3};
     for (int l = 0; l < 3; ++l) {
@@ -163,7 +171,16 @@ sclbm_status hidden_forward(const sclmlp_ctx *c, int Mp, bool transposed) {
         g.ldc = NHID;
         g.CT = transposed ? c->ht(l) : nullptr;
         g.ldct = Mp;
-        TRY(gemm<EPI_RELU>(c, g));
+        if (l == 0 && windows) {
+            g.A = nullptr;
+            g.Af = windows;
+            g.ashift = c->in_shift();
+            g.ascale = c->in_scale();
+            g.arows = n;
+            TRY((gemm<EPI_RELU, true>(c, g)));
+        } else {
+            TRY(gemm<EPI_RELU>(c, g));
+        }
     }
     return SCLBM_OK;
 }
@@ -303,12 +320,17 @@ sclbm_status sclmlp_predict(sclmlp_ctx *c, const float *dev_windows, int64_t n, 
     if (!dev_windows || !dev_out) return fail(SCLBM_EINVAL, "null buffer");
     TRY(use_device(c));
     const int Mp = (int)padded_rows(n);
-    k_prep<false><<<dim3(NIN / 64, Mp / 64), 256, 0, c->stream>>>(dev_windows, nullptr, nullptr, (int)n, (int)n,
-                                                                    c->in_shift(), c->in_scale(), c->at<bf16>(c->lay.x),
-                                                                    nullptr, Mp, c->at<unsigned>(c->lay.bad));
-    HIP_LAUNCHED();
-    TRY(hidden_forward(c, Mp, false));
-    k_out<true><<<Mp / 64, 256, 0, c->stream>>>(c->h(2), c->wb(3), c->P() + OFF_B4, (int)n, c->out_shift(),
+    if (reinterpret_cast<uintptr_t>(dev_windows) % 16 == 0) {
+        TRY(hidden_forward(c, Mp, false, dev_windows, (int)n));  // first layer reads the windows itself
+    } else {
+        k_prep<false><<<dim3(NIN / 64, Mp / 64), 256, 0, c->stream>>>(dev_windows, nullptr, nullptr, (int)n, (int)n,
+                                                                        c->in_shift(), c->in_scale(),
+                                                                        c->at<bf16>(c->lay.x), nullptr, Mp,
+                                                                        c->at<unsigned>(c->lay.bad));
+        HIP_LAUNCHED();
+        TRY(hidden_forward(c, Mp, false));
+    }
+    k_out<true><<<Mp / OUT_ROWS, 256, 0, c->stream>>>(c->h(2), c->wb(3), c->P() + OFF_B4, (int)n, c->out_shift(),
                                                 c->out_scale(), dev_out, nullptr, nullptr, nullptr, 0, nullptr,
                                                 nullptr);
     HIP_LAUNCHED();
@@ -325,7 +347,7 @@ sclbm_status sclmlp_gradients(sclmlp_ctx *c, const float *dev_windows, const flo
     if (!dev_index && ndata < n) return fail(SCLBM_EINVAL, "without an index ndata must be >= n");
     if (!dev_windows || !dev_targets) return fail(SCLBM_EINVAL, "null buffer");
     TRY(use_device(c));
-    const int Mp = (int)padded_rows(n), nb = Mp / 64;
+    const int Mp = (int)padded_rows(n), nb = Mp / 64, nbo = Mp / OUT_ROWS;
     float *G = c->G();
     bf16 *dza = c->at<bf16>(c->lay.dza), *dzb = c->at<bf16>(c->lay.dzb);
     bf16 *dzat = c->at<bf16>(c->lay.dzat), *dzbt = c->at<bf16>(c->lay.dzbt);
@@ -337,11 +359,11 @@ sclbm_status sclmlp_gradients(sclmlp_ctx *c, const float *dev_windows, const flo
                                                              c->at<bf16>(c->lay.xt), Mp, c->at<unsigned>(c->lay.bad));
     HIP_LAUNCHED();
     TRY(hidden_forward(c, Mp, true));
-    k_out<false><<<nb, 256, 0, c->stream>>>(c->h(2), c->wb(3), c->P() + OFF_B4, (int)n, c->out_shift(),
+    k_out<false><<<nbo, 256, 0, c->stream>>>(c->h(2), c->wb(3), c->P() + OFF_B4, (int)n, c->out_shift(),
                                             c->out_scale(), nullptr, dev_targets, dev_index, dev_sym, (int)ndata, dy,
                                             partial);
     HIP_LAUNCHED();
-    k_loss_final<<<1, 64, 0, c->stream>>>(partial, nb, (int)n, dev_loss ? dev_loss : c->at<double>(c->lay.loss),
+    k_loss_final<<<1, 256, 0, c->stream>>>(partial, nbo, (int)n, dev_loss ? dev_loss : c->at<double>(c->lay.loss),
                                           G + OFF_B4);
     HIP_LAUNCHED();
 
