@@ -373,8 +373,8 @@ class Lattice:
 
     def init_fields(self, rho_a, rho_b, u=None, box=0):
         t = self.torch
-        ra = t.as_tensor(np.broadcast_to(rho_a, self.shape), dtype=t.float64).to(self.device).contiguous()
-        rb = t.as_tensor(np.broadcast_to(rho_b, self.shape), dtype=t.float64).to(self.device).contiguous()
+        ra = t.as_tensor(np.array(np.broadcast_to(rho_a, self.shape), dtype=np.float64)).to(self.device)
+        rb = t.as_tensor(np.array(np.broadcast_to(rho_b, self.shape), dtype=np.float64)).to(self.device)
         uu = None
         if u is not None:
             u = np.asarray(u, dtype=np.float64)
