@@ -96,7 +96,7 @@ __global__ __launch_bounds__(NRED_THREADS) void k_surface(const typename Prec<P>
                 double val = 0.0;
                 if (x < g.nx && y < g.ny) {
                     double rho[2], j[2][3];
-                    node_moments<P>(f, ref, g.nnode, ((int64_t)z * g.ny + y) * g.nx + x, rho, j);
+                    node_moments<P>(f, ref, g, ((int64_t)z * g.ny + y) * g.nx + x, rho, j);
                     val = rho[0] - rho[1];
                 }
                 dst[n] = val;
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(NRED_THREADS) void k_drop_mass(const typename Prec<
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.nnode; k += stride) {
         double rho[2], j[2][3];
-        node_moments<P>(f, ref, g.nnode, k, rho, j);
+        node_moments<P>(f, ref, g, k, rho, j);
         if (rho[0] > rho[1]) v[0] += rho[0];
     }
     block_reduce_store<1>(v, partial + (int64_t)blockIdx.y * gridDim.x + blockIdx.x);
@@ -177,14 +177,15 @@ __global__ __launch_bounds__(256) void k_reinject(typename Prec<P>::S *f, __half
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.nnode; k += stride) {
         double rho[2], j[2][3];
-        node_moments<P>(f, ref, g.nnode, k, rho, j);
+        node_moments<P>(f, ref, g, k, rho, j);
         if (!(rho[0] > rho[1])) continue;
         if (Prec<P>::DEV) {
             ref_store(ref + k, float(double(ref_load(ref + k)) * scale));
         } else {
+            const int64_t e = pop_base(g, k);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                typename Prec<P>::S *p = f + (int64_t)i * g.nnode + k;
+                typename Prec<P>::S *p = f + e + (int64_t)i * g.nx;
                 Prec<P>::store(p, R(double(Prec<P>::load(p, R(0))) * scale), R(0));
             }
         }

@@ -27,6 +27,13 @@ struct BoxGeom {
     double xc[3];
 };
 
+// Element offset of direction 0 of node k = (z ny + y) nx + x in one component's
+// population block (row-blocked order [z][y][direction][x]); direction i adds i nx.
+__device__ __forceinline__ int64_t pop_base(const BoxGeom &g, int64_t k) {
+    const int64_t row = k / g.nx;
+    return row * (int64_t)(Q * g.nx) + (k - row * g.nx);
+}
+
 __device__ __forceinline__ void node_xyz(const BoxGeom &g, int64_t k, int &x, int &y, int &z) {
     x = (int)(k % g.nx);
     int64_t t = k / g.nx;
@@ -73,6 +80,7 @@ __global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, __half *re
     }
     const double usq = ux * ux + uy * uy + uz * uz;
     const double rr[2] = {ra, rb};
+    const int64_t e = pop_base(g, k);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         double rref = 0.0;
@@ -83,22 +91,24 @@ __global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, __half *re
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const double fe = equilibrium<double>(i, rr[s], ux, uy, uz, usq);
-            Prec<P>::store(f + (int64_t)(s * Q + i) * g.nnode + k, R(fe), R(w_of<R>(i) * R(rref)));
+            Prec<P>::store(f + (int64_t)s * Q * g.nnode + e + (int64_t)i * g.nx, R(fe), R(w_of<R>(i) * R(rref)));
         }
     }
 }
 
 template <int P>
-__device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, const __half *ref, int64_t N, int64_t k,
-                                             double rho[2], double j[2][3]) {
+__device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, const __half *ref, const BoxGeom &g,
+                                             int64_t k, double rho[2], double j[2][3]) {
     using R = typename Prec<P>::R;
+    const int64_t N = g.nnode;
+    const int64_t e = pop_base(g, k);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         R r = R(0), jx = R(0), jy = R(0), jz = R(0);
         const R rref = Prec<P>::DEV ? R(ref_load(ref + s * N + k)) : R(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R v = R(Prec<P>::load(f + (int64_t)(s * Q + i) * N + k, w_of<R>(i) * rref));
+            const R v = R(Prec<P>::load(f + (int64_t)s * Q * N + e + (int64_t)i * g.nx, w_of<R>(i) * rref));
             r += v;
             if (cx_of(i)) jx += R(cx_of(i)) * v;
             if (cy_of(i)) jy += R(cy_of(i)) * v;
@@ -117,7 +127,7 @@ __global__ __launch_bounds__(256) void k_density(const typename Prec<P>::S *f, c
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= g.nnode) return;
     double rho[2], j[2][3];
-    node_moments<P>(f, ref, g.nnode, k, rho, j);
+    node_moments<P>(f, ref, g, k, rho, j);
     rho_a[k] = rho[0];
     rho_b[k] = rho[1];
 }
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(256) void k_velocity(const typename Prec<P>::S *f, 
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= g.nnode) return;
     double rho[2], j[2][3];
-    node_moments<P>(f, ref, g.nnode, k, rho, j);
+    node_moments<P>(f, ref, g, k, rho, j);
     int x, y, z;
     node_xyz(g, k, x, y, z);
     const double *rf[2] = {rho_a, rho_b};
@@ -205,7 +215,7 @@ __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.nnode; k += stride) {
         double rho[2], j[2][3];
-        node_moments<P>(f, ref, g.nnode, k, rho, j);
+        node_moments<P>(f, ref, g, k, rho, j);
         v[0] += rho[0];
         v[1] += rho[1];
         v[2] += j[0][0] + j[1][0];
