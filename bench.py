@@ -167,7 +167,7 @@ def surrogate_study(train_steps: int = 10000, nsamp: int = 400, log=None):
         "workload": case.name, "boxes": case.nbox, "box": case.n, "radius": case.radius,
         "lattice_steps": (nsamp - 1) * STRIDE, "ensemble_mlups": round(run.mlups, 1),
         "ensemble_hbm_frac": round(run.mlups * 1e6 * 304 / (HBM_PEAK_GBS * 1e9), 4),
-        "ensemble_launch": {"tile_rows": run.launch[0], "zchunk": run.launch[1]},
+        "ensemble_launch": {"tile_rows": run.launch[0], "zchunk": run.launch[1], "tile_waves": run.launch[2]},
         "windows": {"train": int(len(tr.targets)), "held_out": int(len(va.targets)), "samples": 64, "stride": STRIDE},
         "train": {"steps": res.steps, "batch": 256, "seconds": round(res.seconds, 2), "augment": "48 cubic maps"},
         "lbm_samples_per_s": round(run.lbm_samples_per_s, 1),
@@ -194,7 +194,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--launch", type=str, default="", help="tile_rows,zchunk")
+    ap.add_argument("--launch", type=str, default="", help="tile_rows,zchunk[,tile_waves]")
     ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
                     help="c2: the headline 128^3 FP32 box (default); c3: the 256^3 precision study")
     ap.add_argument("--c3-steps", type=int, default=10000)
@@ -232,8 +232,7 @@ def main():
     lat = sc.Lattice(case.n, case.n, case.n, bc="ghost", prec=case.prec, table_len=total_steps, tau=(1.0, 1.0),
                      g_ab=wl.G_AB, rho_b=case.rho_b, mach_max=wl.MACH_MAX)
     if args.launch:
-        ty, zc = (int(v) for v in args.launch.split(","))
-        lat.set_launch(ty, zc)
+        lat.set_launch(*(int(v) for v in args.launch.split(",")))
     lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
     lat.set_gradient_table(tab[:total_steps], 0)
     m0, _ = lat.totals()
@@ -267,7 +266,7 @@ def main():
     mlups = lups / elapsed / 1e6
     bytes_per_lup = 2 * 19 * 2 * 4  # both components, 19 populations, read + write, FP32
     achieved = bytes_per_lup * nodes / (step_ms * 1e-3) / 1e9
-    ty, zc = lat.get_launch()
+    ty, zc, wx = lat.get_launch()
     out = {
         "metric": "MLUPS & % HBM peak (2-comp LBM); surrogate vs LBM samples/sec at <=5% err",
         "value": round(mlups, 2),
@@ -283,7 +282,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "box": case.n, "radius": case.radius, "lattice_steps_per_step": STRIDE,
                    "lattice_steps_timed": STRIDE * K, "tau": case.tau, "g_ab": wl.G_AB,
-                   "storage": "fp32 SoA, 2x19 populations (arithmetic fp64)", "launch": {"tile_rows": ty, "zchunk": zc},
+                   "storage": "fp32 SoA, 2x19 populations (arithmetic fp64)", "launch": {"tile_rows": ty, "zchunk": zc, "tile_waves": wx},
                    "ca_max": round(float(ca.max()), 4), "ca_mean": round(float(ca.mean()), 4),
                    "mass_drift_rel": [float(v) for v in ((m1 - m0) / m0)],
                    "semi_axes_last": [round(float(v), 4) for v in axes[-1]]},

@@ -62,9 +62,9 @@ typedef enum {
 
 typedef enum {
     SCLBM_F64 = 0,    /* FP64 populations, FP64 arithmetic */
-    SCLBM_F32 = 1,    /* FP32 populations, FP32 arithmetic */
-    SCLBM_F16DEV = 2, /* FP16 deviations f_i - w_i rho_ref, FP32 arithmetic */
-    SCLBM_BF16DEV = 3 /* BF16 deviations f_i - w_i rho_ref, FP32 arithmetic */
+    SCLBM_F32 = 1,    /* FP32 populations, FP64 arithmetic */
+    SCLBM_F16DEV = 2, /* FP16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
+    SCLBM_BF16DEV = 3 /* BF16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
 } sclbm_prec;
 
 typedef struct {
@@ -220,19 +220,23 @@ sclbm_status sclbm_state_bytes(const sclbm_ctx *ctx, size_t *bytes);
 sclbm_status sclbm_save(sclbm_ctx *ctx, void *host_buf, size_t bytes);
 sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
 
-/* Launch shape of the step kernel: rows per tile (4 or 8) and planes per
- * z-chunk (>= 1).  Both only change speed, never results. */
-sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk);
-sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk);
+/* Launch shape of the step kernel: a tile of tile_rows rows of tile_waves
+ * 64-node wavefronts, (tile_rows, tile_waves) one of (4, 1), (8, 1), (4, 2), and
+ * planes per z-chunk (>= 1).  A tile as wide as the box's rows lets every
+ * x-shifted store write whole cache lines; the default is (4, 2) for nx > 64,
+ * else (8, 1).  The shape only changes speed, never results.  Pointers of
+ * get_launch may be NULL. */
+sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk, int32_t tile_waves);
+sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);
 
 /* Autotuner: time trial_steps steps (after one warm-up step) for every tile
- * height (4, 8) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz), keep the
- * fastest and set it.  best_ms (may be NULL) receives the best average step
- * time.  The trials overwrite the populations (call it before an init call, or
+ * shape ((4, 1), (8, 1), and (4, 2) when nx > 64) and z-chunk (2, 4, 8, 16,
+ * 32, 64, capped at nz), keep the fastest and set it.  The output pointers
+ * (may be NULL) receive its shape and the best average step time in ms.  The trials overwrite the populations (call it before an init call, or
  * re-initialise after) but restore the time.  In ghost mode every box's table
  * must cover steps n .. n + trial_steps.  Synchronises. */
 sclbm_status sclbm_autotune(sclbm_ctx *ctx, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk,
-                            float *best_ms);
+                            int32_t *tile_waves, float *best_ms);
 
 /* Maffettone-Minale morphology tensor (Sec. 2 Eqs. 1, 2, 5) for ntraj
  * trajectories on the GPU, one thread each, FP64 classical RK4 with `substeps`

@@ -79,7 +79,8 @@ def _load_library():
         "sclbm_set_gradient_table": [P, I32, dp, I64, I64],
         "sclbm_step": [P, I64],
         "sclbm_step_graph": [P, I64],
-        "sclbm_autotune": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float)],
+        "sclbm_autotune": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                           ctypes.POINTER(ctypes.c_float)],
         "sclbm_get_step": [P, ctypes.POINTER(I64)],
         "sclbm_fields": [P, I32, P, P, P],
         "sclbm_totals": [P, I32, dp, dp],
@@ -96,8 +97,8 @@ def _load_library():
         "sclbm_state_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
         "sclbm_save": [P, P, ctypes.c_size_t],
         "sclbm_load": [P, P, ctypes.c_size_t],
-        "sclbm_set_launch": [P, I32, I32],
-        "sclbm_get_launch": [P, ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "sclbm_set_launch": [P, I32, I32, I32],
+        "sclbm_get_launch": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "sclmlp_workspace_bytes": [I64, ctypes.POINTER(ctypes.c_size_t)],
         "sclmlp_create": [I64, P, ctypes.c_size_t, P, ctypes.POINTER(P)],
         "sclmlp_destroy": [P],
@@ -197,11 +198,14 @@ def sclbm_step_graph(ctx, nsteps: int):
 
 
 def sclbm_autotune(ctx, trial_steps: int):
+    """Returns (tile_rows, zchunk, tile_waves, best_ms)."""
     t = ctypes.c_int32()
     z = ctypes.c_int32()
+    w = ctypes.c_int32()
     ms = ctypes.c_float()
-    _check(_lib.sclbm_autotune(ctx, int(trial_steps), ctypes.byref(t), ctypes.byref(z), ctypes.byref(ms)))
-    return t.value, z.value, ms.value
+    _check(_lib.sclbm_autotune(ctx, int(trial_steps), ctypes.byref(t), ctypes.byref(z), ctypes.byref(w),
+                               ctypes.byref(ms)))
+    return t.value, z.value, w.value, ms.value
 
 
 def sclbm_get_step(ctx) -> int:
@@ -283,15 +287,17 @@ def sclbm_load(ctx, buf: np.ndarray):
     _check(_lib.sclbm_load(ctx, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes))
 
 
-def sclbm_set_launch(ctx, tile_rows: int, zchunk: int):
-    _check(_lib.sclbm_set_launch(ctx, int(tile_rows), int(zchunk)))
+def sclbm_set_launch(ctx, tile_rows: int, zchunk: int, tile_waves: int = 1):
+    _check(_lib.sclbm_set_launch(ctx, int(tile_rows), int(zchunk), int(tile_waves)))
 
 
 def sclbm_get_launch(ctx):
+    """Returns (tile_rows, zchunk, tile_waves)."""
     t = ctypes.c_int32()
     z = ctypes.c_int32()
-    _check(_lib.sclbm_get_launch(ctx, ctypes.byref(t), ctypes.byref(z)))
-    return t.value, z.value
+    w = ctypes.c_int32()
+    _check(_lib.sclbm_get_launch(ctx, ctypes.byref(t), ctypes.byref(z), ctypes.byref(w)))
+    return t.value, z.value, w.value
 
 
 def sclbm_mm_integrate(dev_A_ptr, ntraj, nrows, tau_d, chi, substeps, record_every, dev_M0_ptr, dev_M_ptr, stream):
@@ -400,8 +406,8 @@ class Lattice:
         an init).  Results are cached in $XDG_CACHE_HOME/sclbm/tuning.json keyed
         by device, box shape, boxes, precision and boundary mode."""
         import json
-        key = "%s|%dx%dx%d|%d|%d|%d" % (self.torch.cuda.get_device_properties(self.device).name, self.nx, self.ny,
-                                        self.nz, self.nbox, self.cfg.prec, self.cfg.bc)
+        key = "%s|%dx%dx%d|%d|%d|%d|rowtiles" % (self.torch.cuda.get_device_properties(self.device).name, self.nx,
+                                                 self.ny, self.nz, self.nbox, self.cfg.prec, self.cfg.bc)
         path = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "sclbm", "tuning.json")
         table = {}
         if cache and os.path.exists(path):
@@ -411,19 +417,19 @@ class Lattice:
             except (OSError, ValueError):
                 table = {}
         if key in table:
-            ty, zc = table[key]["tile_rows"], table[key]["zchunk"]
-            self.set_launch(ty, zc)
-            return ty, zc, table[key]["ms"]
-        ty, zc, ms = sclbm_autotune(self.ctx, trial_steps)
+            ty, zc, wx = table[key]["tile_rows"], table[key]["zchunk"], table[key]["tile_waves"]
+            self.set_launch(ty, zc, wx)
+            return ty, zc, wx, table[key]["ms"]
+        ty, zc, wx, ms = sclbm_autotune(self.ctx, trial_steps)
         if cache:
-            table[key] = {"tile_rows": ty, "zchunk": zc, "ms": ms}
+            table[key] = {"tile_rows": ty, "zchunk": zc, "tile_waves": wx, "ms": ms}
             try:
                 os.makedirs(os.path.dirname(path), exist_ok=True)
                 with open(path, "w") as fh:
                     json.dump(table, fh, indent=1)
             except OSError:
                 pass
-        return ty, zc, ms
+        return ty, zc, wx, ms
 
     def synchronize(self):
         self.stream.synchronize()
@@ -493,8 +499,8 @@ class Lattice:
     def load(self, buf: np.ndarray):
         sclbm_load(self.ctx, np.ascontiguousarray(buf))
 
-    def set_launch(self, tile_rows, zchunk):
-        sclbm_set_launch(self.ctx, tile_rows, zchunk)
+    def set_launch(self, tile_rows, zchunk, tile_waves=1):
+        sclbm_set_launch(self.ctx, tile_rows, zchunk, tile_waves)
 
     def get_launch(self):
         return sclbm_get_launch(self.ctx)

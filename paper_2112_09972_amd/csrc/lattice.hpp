@@ -80,6 +80,19 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
 // wref (1 + d); any consistent reciprocal will do.
 __device__ __forceinline__ float rel_dev(float v, float wref) { return (v - wref) * __builtin_amdgcn_rcpf(wref); }
 
+// Lane l of a wavefront receives lane l - CX's value (CX = +1 or -1): the DPP
+// whole-wave shift by one lane (wave_shr:1 / wave_shl:1 of the gfx9 family).  The
+// lane that has no source keeps 0.  Every lane of the wave must be active.
+template <int CX>
+__device__ __forceinline__ uint32_t lane_shift(uint32_t v) {
+    static_assert(CX == 1 || CX == -1, "one-lane shifts only");
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CX > 0 ? 0x138 : 0x130, 0xf, 0xf, false));
+}
+template <int CX>
+__device__ __forceinline__ uint64_t lane_shift(uint64_t v) {
+    return uint64_t(lane_shift<CX>(uint32_t(v))) | (uint64_t(lane_shift<CX>(uint32_t(v >> 32))) << 32);
+}
+
 template <int P>
 struct Prec;
 template <>
@@ -93,8 +106,13 @@ struct Prec<SCLBM_F64> {
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R /*wref*/) {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
     }
-    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R /*wref*/) {
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, vo, so, 0);
+    using B = uint64_t;  // stored bits
+    static __device__ __forceinline__ B enc(R v, R /*wref*/) { return __builtin_bit_cast(uint64_t, v); }
+    static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, b), r, vo, so, 0);
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
+        bstore_bits(r, vo, so, enc(v, wref));
     }
 };
 template <>
@@ -108,8 +126,13 @@ struct Prec<SCLBM_F32> {
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R /*wref*/) {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
-    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R /*wref*/) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, float(v)), r, vo, so, 0);
+    using B = uint32_t;
+    static __device__ __forceinline__ B enc(R v, R /*wref*/) { return __builtin_bit_cast(uint32_t, float(v)); }
+    static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
+        __builtin_amdgcn_raw_buffer_store_b32(b, r, vo, so, 0);
+    }
+    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
+        bstore_bits(r, vo, so, enc(v, wref));
     }
 };
 template <>
@@ -124,9 +147,15 @@ struct Prec<SCLBM_F16DEV> {
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
         return wref + wref * __half2float(__builtin_bit_cast(__half, b));
     }
+    using B = uint32_t;  // the 16 stored bits in the low half
+    static __device__ __forceinline__ B enc(R v, R wref) {
+        return __builtin_bit_cast(unsigned short, __float2half_rn(rel_dev(v, wref)));
+    }
+    static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)b, r, vo, so, 0);
+    }
     static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half_rn(rel_dev(v, wref))), r,
-                                              vo, so, 0);
+        bstore_bits(r, vo, so, enc(v, wref));
     }
 };
 template <>
@@ -141,9 +170,15 @@ struct Prec<SCLBM_BF16DEV> {
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
         return wref + wref * __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
     }
+    using B = uint32_t;
+    static __device__ __forceinline__ B enc(R v, R wref) {
+        return __builtin_bit_cast(unsigned short, __float2bfloat16(rel_dev(v, wref)));
+    }
+    static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)b, r, vo, so, 0);
+    }
     static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(rel_dev(v, wref))), r,
-                                              vo, so, 0);
+        bstore_bits(r, vo, so, enc(v, wref));
     }
 };
 

@@ -119,12 +119,13 @@ struct sclbm_ctx {
     int64_t n;        // time of the state
     int par;          // which population buffer holds f(n): 0 -> f0
     int tile_rows;    // TY
+    int tile_waves;   // WX: wavefronts per tile row (tile width 64 WX)
     int zchunk;
     std::vector<int64_t> tab_first, tab_len;  // host copies, per box
-    // captured step loop: valid for (graph_steps, graph_par, graph_ty, graph_zc)
+    // captured step loop: valid for (graph_steps, graph_par, graph_ty, graph_wx, graph_zc)
     hipGraphExec_t graph_exec = nullptr;
     int64_t graph_steps = 0;
-    int graph_par = -1, graph_ty = 0, graph_zc = 0;
+    int graph_par = -1, graph_ty = 0, graph_wx = 0, graph_zc = 0;
     int64_t N;
     BoxGeom geom;
 
@@ -157,36 +158,45 @@ sclbm_status check_box(const sclbm_ctx *c, int32_t box, bool allow_all) {
     return SCLBM_OK;
 }
 
+// Tile shapes of the step kernel: (rows, wavefronts per row).
+bool valid_tile(int ty, int wx) { return (ty == 4 && (wx == 1 || wx == 2)) || (ty == 8 && wx == 1); }
+
+// Default tile: whole 128-wide rows where the box is wider than one wavefront
+// (every x-shifted store then writes whole cache lines), else 64 x 8.
+void default_tile(const sclbm_config &c, int &ty, int &wx) {
+    wx = c.nx > 64 ? 2 : 1;
+    ty = wx == 2 ? 4 : 8;
+}
+
 // z-chunk so that the grid holds about two resident waves per SIMD
-// (256 CUs x 4 SIMDs x 2 waves = 2048 waves = 2048 / TY workgroups).
-int default_zchunk(const sclbm_config &c, int ty) {
-    const long tiles = long((c.nx + 63) / 64) * long((c.ny + ty - 1) / ty) * c.nbox;
-    const long groups = 2048 / ty;
+// (256 CUs x 4 SIMDs x 2 waves = 2048 waves = 2048 / (TY WX) workgroups).
+int default_zchunk(const sclbm_config &c, int ty, int wx) {
+    const long tiles = long((c.nx + 64 * wx - 1) / (64 * wx)) * long((c.ny + ty - 1) / ty) * c.nbox;
+    const long groups = 2048 / (ty * wx);
     long zc = (tiles * c.nz + groups - 1) / groups;
     zc = std::max(2L, std::min(zc, long(c.nz)));
     return int(zc);
 }
 
-// Launch of the step kernel for precision P and tile rows TY.
-template <int P, int TY>
-hipError_t launch_step_ty(sclbm_ctx *c, const StepArgs &a) {
-    dim3 block(64, TY, 1);
-    dim3 grid((c->cfg.nx + 63) / 64, (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
+// Launch of the step kernel for precision P and a tile of TY rows of WX wavefronts.
+template <int P, int TY, int WX>
+hipError_t launch_step_tile(sclbm_ctx *c, const StepArgs &a) {
+    dim3 block(64 * WX, TY, 1);
+    dim3 grid((c->cfg.nx + 64 * WX - 1) / (64 * WX), (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
     // register budget: two waves per SIMD (up to 256 VGPRs); a tighter budget spills
     constexpr int WAVES = 2;
     if (c->cfg.bc == SCLBM_BC_GHOST)
-        hipLaunchKernelGGL((k_step<P, TY, true, WAVES>), grid, block, 0, c->stream, a);
+        hipLaunchKernelGGL((k_step<P, TY, WX, true, WAVES>), grid, block, 0, c->stream, a);
     else
-        hipLaunchKernelGGL((k_step<P, TY, false, WAVES>), grid, block, 0, c->stream, a);
+        hipLaunchKernelGGL((k_step<P, TY, WX, false, WAVES>), grid, block, 0, c->stream, a);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_step(sclbm_ctx *c, const StepArgs &a) {
-    switch (c->tile_rows) {
-        case 8: return launch_step_ty<P, 8>(c, a);
-        default: return launch_step_ty<P, 4>(c, a);
-    }
+    if (c->tile_waves == 2) return launch_step_tile<P, 4, 2>(c, a);
+    if (c->tile_rows == 8) return launch_step_tile<P, 8, 1>(c, a);
+    return launch_step_tile<P, 4, 1>(c, a);
 }
 
 hipError_t launch_step_prec(sclbm_ctx *c, const StepArgs &a) {
@@ -381,8 +391,8 @@ sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t b
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->n = 0;
     c->par = 0;
-    c->tile_rows = 8;
-    c->zchunk = default_zchunk(*cfg, 8);
+    default_tile(*cfg, c->tile_rows, c->tile_waves);
+    c->zchunk = default_zchunk(*cfg, c->tile_rows, c->tile_waves);
     c->tab_first.assign(cfg->nbox, 0);
     c->tab_len.assign(cfg->nbox, 0);
     c->N = int64_t(cfg->nx) * cfg->ny * cfg->nz;
@@ -546,7 +556,7 @@ sclbm_status sclbm_step_graph(sclbm_ctx *c, int64_t nsteps) {
     if (nsteps < 2 || (nsteps & 1)) return fail(SCLBM_EINVAL, "nsteps must be even and >= 2");
     if ((st = check_table(c, nsteps))) return st;
     if (!c->graph_exec || c->graph_steps != nsteps || c->graph_par != c->par || c->graph_ty != c->tile_rows ||
-        c->graph_zc != c->zchunk) {
+        c->graph_wx != c->tile_waves || c->graph_zc != c->zchunk) {
         drop_graph(c);
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -565,6 +575,7 @@ sclbm_status sclbm_step_graph(sclbm_ctx *c, int64_t nsteps) {
         c->graph_steps = nsteps;
         c->graph_par = c->par;
         c->graph_ty = c->tile_rows;
+        c->graph_wx = c->tile_waves;
         c->graph_zc = c->zchunk;
     }
     HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
@@ -572,26 +583,29 @@ sclbm_status sclbm_step_graph(sclbm_ctx *c, int64_t nsteps) {
     return SCLBM_OK;
 }
 
-sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk, float *best_ms) {
+sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk,
+                            int32_t *tile_waves, float *best_ms) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
     if (trial_steps < 1 || trial_steps > 100000) return fail(SCLBM_EINVAL, "trial_steps must be in [1, 100000]");
     if ((st = check_table(c, int64_t(trial_steps) + 1))) return st;
-    const int ty_keep = c->tile_rows, zc_keep = c->zchunk;
+    const int ty_keep = c->tile_rows, wx_keep = c->tile_waves, zc_keep = c->zchunk;
     const int64_t n0 = c->n;
     const int par0 = c->par;
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
     float best = -1.0f;
-    int bty = ty_keep, bzc = zc_keep;
-    const int tys[2] = {4, 8};
+    int bty = ty_keep, bwx = wx_keep, bzc = zc_keep;
+    const int tys[3] = {4, 8, 4}, wxs[3] = {1, 1, 2};
     const int zcs[6] = {2, 4, 8, 16, 32, 64};
     sclbm_status result = SCLBM_OK;
-    for (int ti = 0; ti < 2 && result == SCLBM_OK; ++ti)
+    for (int ti = 0; ti < 3 && result == SCLBM_OK; ++ti)
         for (int zi = 0; zi < 6 && result == SCLBM_OK; ++zi) {
             if (zcs[zi] > c->cfg.nz && zi > 0 && zcs[zi - 1] >= c->cfg.nz) continue;
+            if (wxs[ti] > 1 && c->cfg.nx <= 64) continue;  // a second wavefront would hold no nodes
             c->tile_rows = tys[ti];
+            c->tile_waves = wxs[ti];
             c->zchunk = std::min(zcs[zi], c->cfg.nz);
             int64_t clk[2] = {n0, n0};
             hipError_t e = hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream);
@@ -611,6 +625,7 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
             if (best < 0.0f || ms < best) {
                 best = ms;
                 bty = c->tile_rows;
+                bwx = c->tile_waves;
                 bzc = c->zchunk;
             }
         }
@@ -624,14 +639,17 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
     c->par = par0;
     if (result != SCLBM_OK) {
         c->tile_rows = ty_keep;
+        c->tile_waves = wx_keep;
         c->zchunk = zc_keep;
         return result;
     }
     c->tile_rows = bty;
+    c->tile_waves = bwx;
     c->zchunk = bzc;
     drop_graph(c);
     if (tile_rows) *tile_rows = bty;
     if (zchunk) *zchunk = bzc;
+    if (tile_waves) *tile_waves = bwx;
     if (best_ms) *best_ms = best;
     return SCLBM_OK;
 }
@@ -902,22 +920,25 @@ sclbm_status sclbm_load(sclbm_ctx *c, const void *host_buf, size_t bytes) {
     return SCLBM_OK;
 }
 
-sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk) {
+sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk, int32_t tile_waves) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
-    if (tile_rows != 4 && tile_rows != 8) return fail(SCLBM_EINVAL, "tile_rows must be 4 or 8");
+    if (!valid_tile(tile_rows, tile_waves))
+        return fail(SCLBM_EINVAL, "tile (rows %d, waves %d) must be (4, 1), (8, 1) or (4, 2)", tile_rows, tile_waves);
     if (zchunk < 1) return fail(SCLBM_EINVAL, "zchunk must be >= 1");
     c->tile_rows = tile_rows;
+    c->tile_waves = tile_waves;
     c->zchunk = std::min<int32_t>(zchunk, c->cfg.nz);
     drop_graph(c);
     return SCLBM_OK;
 }
 
-sclbm_status sclbm_get_launch(const sclbm_ctx *c, int32_t *tile_rows, int32_t *zchunk) {
+sclbm_status sclbm_get_launch(const sclbm_ctx *c, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
     if (tile_rows) *tile_rows = c->tile_rows;
     if (zchunk) *zchunk = c->zchunk;
+    if (tile_waves) *tile_waves = c->tile_waves;
     return SCLBM_OK;
 }
 

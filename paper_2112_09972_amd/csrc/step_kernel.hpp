@@ -85,35 +85,51 @@ __device__ __forceinline__ void eq_pair(R cu, R aa, R rho3, R rho45, R &plus, R 
     minus = sym - asym;
 }
 
-template <int P, int TY, bool GHOST, int WAVES>
-__global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
+// The ten directions with c_x != 0 and their slots in the deferred-store arrays:
+// odd directions have c_x = +1, even ones c_x = -1.
+__host__ __device__ constexpr int xdir_of(int j) { return j < 2 ? j + 1 : j + 5; }
+constexpr int NXD = 10;
+
+template <int P, int TY, int WX, bool GHOST, int WAVES>
+__global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     using S = typename Prec<P>::S;
     using W = typename Prec<P>::W;
     using R = typename Prec<P>::R;
+    using B = typename Prec<P>::B;
     using C = R;  // collision arithmetic
-    constexpr int LW = 66;  // 64 + ring
+    constexpr int TXW = 64 * WX;  // tile width: WX wavefronts per row
+    constexpr int LW = TXW + 2;   // with the ring
     constexpr uint32_t EB = sizeof(S);
     __shared__ R lds[4][2][TY + 2][LW];
+    // values that cross a wavefront edge in x, by plane parity, component, c_x != 0
+    // direction, row and wave boundary b (b = 0: the tile's left edge; b = WX: right)
+    __shared__ B edge[2][2][NXD][TY][WX + 1];
 
     const int lx = threadIdx.x, ly = threadIdx.y;
-    const int tid = ly * 64 + lx;
+    const int tid = ly * TXW + lx;
+    const int lane = lx & 63, wv = lx >> 6;
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8
     // XCDs by linear id, so give XCD k one contiguous run of tiles (x fastest,
     // then y, then z-chunk and box).  Neighbouring tiles then share an L2 for
-    // their ring re-reads and for the partial cache lines of shifted stores.
+    // their ring re-reads.
     const uint32_t nbx = gridDim.x, nby = gridDim.y;
     const uint32_t nb = nbx * nby * gridDim.z;
     const uint32_t lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
     const uint32_t q8 = nb / 8, r8 = nb % 8, xcd = lin % 8, k8 = lin / 8;
     const uint32_t tile = xcd < r8 ? xcd * (q8 + 1) + k8 : r8 * (q8 + 1) + (xcd - r8) * q8 + k8;
     const int bx = int(tile % nbx), by = int((tile / nbx) % nby), bz = int(tile / (nbx * nby));
-    const int x0 = bx * 64, y0 = by * TY;
+    const int x0 = bx * TXW, y0 = by * TY;
     const int box = bz / a.nzc;
     const int zs = (bz % a.nzc) * a.zchunk;
     const int ze = min(zs + a.zchunk, a.nz);
     const int x = x0 + lx, y = y0 + ly;
     const bool valid = (x < a.nx) && (y < a.ny);
-    const int tw = min(64, a.nx - x0), th = min(TY, a.ny - y0);  // valid tile extent
+    const int tw = min(TXW, a.nx - x0), th = min(TY, a.ny - y0);  // valid tile extent
+    const int nw = (tw + 63) >> 6;                                 // wavefronts per row holding nodes
+    const int wlast = min(63, tw - 1 - 64 * wv);                   // this wave's last lane in the box
+    const bool wave_on = (y < a.ny) && (wv < nw);                  // uniform over the wavefront
+    const bool left_face = x0 == 0, right_face = x0 + tw == a.nx;
+    const bool span = left_face && right_face;                     // the tile holds whole rows
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const uint32_t N = uint32_t(a.nnode);
     const uint32_t nxy = uint32_t(nx) * uint32_t(ny);
@@ -135,16 +151,79 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
     __half *ref_out = DEV ? a.ref_dst + (int64_t)box * 2 * N : nullptr;
     const R rhob[2] = {R(a.rho_b[0]), R(a.rho_b[1])};
 
-    static_assert(TY >= 4, "one ring node per thread needs 2 (64 + 2) + 2 TY <= 64 TY");
+    static_assert(2 * (TXW + 2) + 2 * TY <= TXW * TY, "one ring node per thread");
     const int ringN = 2 * (tw + 2) + 2 * th;
     const int nplanes = (ze - zs) + 2;
+
+    // Stores of the c_x != 0 populations of the plane collided one iteration
+    // earlier (plane zp, edge parity par).  Lane l writes its own node's slot with
+    // the value of lane l - c_x (a whole-wave lane shift), so that every store of a
+    // wavefront covers 64 aligned, consecutive elements and writes whole cache lines;
+    // the lane whose source lies in the next wavefront takes it from LDS, and at an
+    // x face the ghost population put there in its place.  A tile that does not hold
+    // whole rows also writes the one value that leaves it, from its edge lane.
+    B pend[2][NXD];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int j = 0; j < NXD; ++j) pend[s][j] = B(0);
+    auto flush = [&](int zp, int par) {
+        if (!wave_on) return;
+#pragma unroll
+        for (int j = 0; j < NXD; ++j) {
+            const int i = xdir_of(j);
+            const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+            int yd = y + cy, zd = zp + cz;
+            bool out = false;
+            if (GHOST) {
+                out = yd < 0 || yd >= ny || zd < 0 || zd >= nz;
+            } else {
+                yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+                zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
+            }
+            const uint32_t row = (uint32_t(zd) * uint32_t(ny) + uint32_t(yd)) * qnx + uint32_t(i) * uint32_t(nx);
+            // receiving lane, its source and whether it is written here
+            bool ok = lane <= wlast && !out;
+            int b = 0;
+            bool from_edge = false;
+            if (cx > 0 && lane == 0) {
+                from_edge = true;
+                if (wv > 0) b = wv;
+                else if (GHOST) { b = 0; ok = ok && left_face; }
+                else { b = nw; ok = ok && span; }
+            }
+            if (cx < 0 && lane == wlast) {
+                from_edge = true;
+                if (wv < nw - 1) b = wv + 1;
+                else if (GHOST) { b = nw; ok = ok && right_face; }
+                else { b = 0; ok = ok && span; }
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const B sh = cx > 0 ? lane_shift<1>(pend[s][j]) : lane_shift<-1>(pend[s][j]);
+                const B v = from_edge ? edge[par][s][j][ly][b] : sh;
+                Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0, v);
+            }
+            if (!span) {
+                // the value that leaves the tile: c_x = +1 from the last lane, -1 from lane 0
+                const bool src_lane = cx > 0 ? (lane == wlast && wv == nw - 1) : (lane == 0 && wv == 0);
+                int xd = cx > 0 ? x0 + tw : x0 - 1;
+                bool go = src_lane && !out;
+                if (GHOST) go = go && (cx > 0 ? !right_face : !left_face);
+                else xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    Prec<P>::bstore_bits(rd[s], go ? (row + uint32_t(xd)) * EB : kOOB, 0, pend[s][j]);
+            }
+        }
+    };
 
     W fprev[2][Q], fcur[2][Q];
     for (int k = 0; k < nplanes; ++k) {
         const int z = zs - 1 + k;
         const int slot = k & 3;
         // ---- 1. densities of plane z: own node (into the register window) and one
-        // ring node per thread (ringN <= 64 TY for TY >= 4) ----
+        // ring node per thread ----
         bool own_in = false, ring_on = false, ring_in = false;
         uint32_t own_vo = 0, ring_vo = 0, own_nd = 0, ring_nd = 0;  // population byte offsets, node indices
         int rsx = 0, rsy = 0;
@@ -217,9 +296,14 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
             lds[slot][1][rsy][rsx] = rr[1];
         }
         __syncthreads();
+        // ---- 2. the c_x != 0 stores of the plane collided one iteration ago (their
+        // edge values are visible after the barrier) ----
+        if (k >= 3) flush(z - 2, (k - 1) & 1);
         if (k >= 2) {
-        // ---- 2. collide plane z-1 and push ----
+        // ---- 3. collide plane z-1: c_x = 0 populations are stored now, the others
+        // after the next barrier ----
         const int zc = z - 1;
+        const int par = k & 1;
         const uint32_t node = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
         const uint32_t elem = (uint32_t(zc) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(x);
         const uint32_t vo = elem * EB;
@@ -288,25 +372,32 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                         if (i == 0) pst = C(rho[s]) - psum;
                         else psum += pst;
                     }
-                    uint32_t dvo;
-                    if (GHOST) {
-                        const bool out = (cx_of(i) < 0 && xlo) || (cx_of(i) > 0 && xhi) || (cy_of(i) < 0 && ylo) ||
-                                         (cy_of(i) > 0 && yhi) || (cz_of(i) < 0 && zlo) || (cz_of(i) > 0 && zhi);
-                        const int shift = cx_of(i) + (cy_of(i) + cz_of(i) * ny) * int(qnx);
-                        dvo = out ? kOOB : uint32_t(int(elem) + shift) * EB + uint32_t(i) * plane_bytes;
-                    } else {
-                        int dx = x + cx_of(i), dy = y + cy_of(i), dz = zc + cz_of(i);
-                        dx = dx < 0 ? dx + nx : (dx >= nx ? dx - nx : dx);
-                        dy = dy < 0 ? dy + ny : (dy >= ny ? dy - ny : dy);
-                        dz = dz < 0 ? dz + nz : (dz >= nz ? dz - nz : dz);
-                        dvo = ((uint32_t(dz) * uint32_t(ny) + uint32_t(dy)) * qnx + uint32_t(dx)) * EB +
-                              uint32_t(i) * plane_bytes;
-                    }
                     // deviation formats: relative to the destination's density at time n,
                     // rounded as the destination's own thread stores it below
                     const C dref = DEV ? C(ref_round(float(lds[(k - 1 + cz_of(i)) & 3][s][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)])))
                                        : C(0);
-                    Prec<P>::bstore(rd[s], dvo, 0, pst, w_of<C>(i) * dref);
+                    const B bits = Prec<P>::enc(pst, w_of<C>(i) * dref);
+                    if (cx_of(i) != 0) {
+                        const int jx = i < 3 ? i - 1 : i - 5;
+                        pend[s][jx] = bits;
+                        if (cx_of(i) > 0 && lane == wlast) edge[par][s][jx][ly][wv + 1] = bits;
+                        if (cx_of(i) < 0 && lane == 0) edge[par][s][jx][ly][wv] = bits;
+                        return;
+                    }
+                    uint32_t dvo;
+                    if (GHOST) {
+                        const bool out = (cy_of(i) < 0 && ylo) || (cy_of(i) > 0 && yhi) || (cz_of(i) < 0 && zlo) ||
+                                         (cz_of(i) > 0 && zhi);
+                        const int shift = (cy_of(i) + cz_of(i) * ny) * int(qnx);
+                        dvo = out ? kOOB : uint32_t(int(elem) + shift) * EB + uint32_t(i) * plane_bytes;
+                    } else {
+                        int dy = y + cy_of(i), dz = zc + cz_of(i);
+                        dy = dy < 0 ? dy + ny : (dy >= ny ? dy - ny : dy);
+                        dz = dz < 0 ? dz + nz : (dz >= nz ? dz - nz : dz);
+                        dvo = ((uint32_t(dz) * uint32_t(ny) + uint32_t(dy)) * qnx + uint32_t(x)) * EB +
+                              uint32_t(i) * plane_bytes;
+                    }
+                    Prec<P>::bstore_bits(rd[s], dvo, 0, bits);
                 };
                 if (DEV) ref_store(ref_out + s * N + node, float(rho[s]));
 #pragma unroll
@@ -324,28 +415,31 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                 push(0, aa);
             }
         }
-        if (GHOST && y < ny) {
-            // Populations streaming in from ghost nodes: the ghost at x_g = x - c_i
-            // holds g_eq(rho_b, A (x_g - x_c)).
+        if (GHOST && wave_on) {
+            // Populations streaming in from ghost nodes, which hold
+            // g_eq(rho_b, A (x_g - x_c)).
             const double *Arow = a.atab + ((int64_t)box * a.table_len + (n - a.tab_first[box])) * 9;
             R Am[9];  // read once: the stores below may alias the table as far as the compiler knows
 #pragma unroll
             for (int q = 0; q < 9; ++q) Am[q] = R(__builtin_nontemporal_load(Arow + q));
-            // (a) x faces, which every row touches: the lanes of the wave share the
-            // work, lane j writing direction j/2 of the five with c_x pointing into
-            // the box, component j%2, for the row's face node.
-            const bool row_lo = (x0 == 0), row_hi = (x0 + tw == nx);
-            for (int side = 0; side < 2; ++side) {
-                if (!(side ? row_hi : row_lo) || lx >= 10) continue;
-                const int fx = side ? nx - 1 : 0;
+            // (a) Ghosts beside this row at x = -1 and x = nx: their five populations
+            // with c_x pointing into the box stream into the face nodes of the rows
+            // y + c_y, z + c_z; they take the place, in the deferred stores, of the
+            // value a left or right neighbour would have pushed.  Lanes 0-9 of the
+            // first wavefront do the left side, lanes 16-25 of the last the right,
+            // lane 2m + s taking incoming direction m of component s.
+            const int side = lane < 16 ? 0 : 1;
+            const int q = lane - 16 * side;
+            if (q < 10 && (side ? (right_face && wv == nw - 1) : (left_face && wv == 0))) {
                 const int sgn = side ? -1 : 1;  // c_x of the incoming directions
-                const int m = lx >> 1, s = lx & 1;
-                // incoming direction (sgn, cyv, czv): m = 0..4 -> (0,0), (1,0), (-1,0), (0,1), (0,-1)
+                const int m = q >> 1, s = q & 1;
+                // m = 0..4 -> (c_y, c_z) = (0,0), (1,0), (-1,0), (0,1), (0,-1)
                 const int cyv = m == 1 ? 1 : (m == 2 ? -1 : 0);
                 const int czv = m == 3 ? 1 : (m == 4 ? -1 : 0);
                 const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
                                         : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
-                const R dxg = R(fx - sgn) - R(a.xc[0]), dyg = R(y - cyv) - R(a.xc[1]), dzg = R(zc - czv) - R(a.xc[2]);
+                const int fx = side ? nx - 1 : 0;  // the receiving face node's x
+                const R dxg = R(fx - sgn) - R(a.xc[0]), dyg = R(y) - R(a.xc[1]), dzg = R(zc) - R(a.xc[2]);
                 const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
                 const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
                 const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
@@ -353,13 +447,14 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                 const R usq = gx * gx + gy * gy + gz * gz;
                 const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
                 const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
-                const uint32_t fnode = (uint32_t(zc) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(fx);
-                const R fref = DEV ? R(ref_round(float(lds[(k - 1) & 3][s][ly + 1][fx - x0 + 1]))) : R(0);
-                Prec<P>::bstore(s ? rd[1] : rd[0], fnode * EB + uint32_t(idx) * plane_bytes, 0, geq, wgt * fref);
+                // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
+                const R fref = DEV ? R(ref_round(float(lds[(k - 1 + czv) & 3][s][ly + 1 + cyv][fx - x0 + 1]))) : R(0);
+                const int jx = idx < 3 ? idx - 1 : idx - 5;
+                edge[par][s][jx][ly][side ? nw : 0] = Prec<P>::enc(geq, wgt * fref);
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
-            // the directions whose source leaves the box through y or z and that
-            // the x-face pass has not written.
+            // the directions whose source lies outside the box in y or z, edges
+            // and corners included.
             if (valid && (ylo || yhi || zlo || zhi)) {
                 const R dx0 = R(x) - R(a.xc[0]), dy0 = R(y) - R(a.xc[1]), dz0 = R(zc) - R(a.xc[2]);
                 // not unrolled: only rows and planes on a y or z face take this path
@@ -367,8 +462,7 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
                 for (int i = 1; i < Q; ++i) {
                     const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
                     const bool from_yz = (cy > 0 && ylo) || (cy < 0 && yhi) || (cz > 0 && zlo) || (cz < 0 && zhi);
-                    const bool from_x = (cx > 0 && xlo) || (cx < 0 && xhi);
-                    if (!from_yz || from_x) continue;
+                    if (!from_yz) continue;
                     const R dxg = dx0 - R(cx), dyg = dy0 - R(cy), dzg = dz0 - R(cz);
                     const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
                     const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
@@ -386,12 +480,15 @@ __global__ __launch_bounds__(64 * TY, WAVES) void k_step(StepArgs a) {
             }
         }
         }  // k >= 2
-        // ---- 3. roll the register window ----
+        // ---- 4. roll the register window ----
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int i = 0; i < Q; ++i) fprev[s][i] = fcur[s][i];
     }
+    // the last collided plane's deferred stores
+    __syncthreads();
+    flush(ze - 1, (nplanes - 1) & 1);
 }
 
 }  // namespace sclbm

@@ -117,7 +117,7 @@ def generate(case: wl.BoxCase, nsamp: int, *, autotune: bool = True, device="cud
     samples = np.stack([t[::stride][:nsamp] for t in tabs])
     return EnsembleRun(n=n, radius=case.radius, stride=stride, samples=samples, semi_axes=axes, r_eq=req,
                        deformation=dd, seconds=seconds, lattice_updates=float(n ** 3) * nbox * steps,
-                       launch=tuple(launch[:2]), tables=tabs)
+                       launch=tuple(launch[:3]), tables=tabs)
 
 
 @dataclass

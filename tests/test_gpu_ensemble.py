@@ -87,9 +87,9 @@ def test_autotune_keeps_results(sc):
     A = wl.simple_shear(0.002)
     lat = sc.Lattice(n, n, n, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
     lat.set_gradient_table(np.tile(A, (steps, 1)), 0)
-    ty, zc, ms = sc.sclbm_autotune(lat.ctx, 3)
-    assert ty in (4, 8) and 1 <= zc <= n and ms > 0
-    assert lat.get_launch() == (ty, zc)
+    ty, zc, wx, ms = sc.sclbm_autotune(lat.ctx, 3)
+    assert (ty, wx) in ((4, 1), (8, 1)) and 1 <= zc <= n and ms > 0   # nx <= 64: one wavefront per row
+    assert lat.get_launch() == (ty, zc, wx)
     assert lat.step_count == 0
     lat.init_droplet(lat.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
     lat.step(steps)

@@ -82,11 +82,15 @@ def test_c1_droplet_shear_parity_500_steps(sc, prec):
 
 
 @pytest.mark.parametrize("bc", ["ghost", "periodic"])
-@pytest.mark.parametrize("launch", [(4, 1), (4, 3), (8, 100)])
-def test_ragged_box_all_launch_shapes(sc, bc, launch):
-    """nx = 70 spans two x-tiles with a 6-wide tail; ny, nz ragged against every
-    tile height and z-chunk."""
-    nxyz = (70, 13, 11)
+@pytest.mark.parametrize("launch,nx", [((4, 1, 1), 70), ((4, 3, 1), 70), ((8, 100, 1), 70), ((4, 1, 2), 70),
+                                       ((4, 3, 2), 70), ((4, 2, 2), 150), ((4, 5, 2), 45)])
+def test_ragged_box_all_launch_shapes(sc, bc, launch, nx):
+    """nx = 70: two 64-wide x-tiles with a 6-wide tail, or one 128-wide tile
+    whose second wavefront holds 6 nodes; nx = 150: a 128-wide tile and a
+    22-wide one (values cross between workgroups); nx = 45: one partial
+    wavefront (periodic wrap inside it).  ny, nz ragged against every tile
+    height and z-chunk."""
+    nxyz = (nx, 13, 11)
     steps = 30
     A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
     lat, o = make_pair(sc, None, nxyz=nxyz, bc=bc, R=4.0, A=A if bc == "ghost" else None, steps=steps)
@@ -103,13 +107,13 @@ def test_ragged_box_all_launch_shapes(sc, bc, launch):
 def test_launch_shape_does_not_change_bits(sc):
     A = np.array([0.0, 0.0, 0.003, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0])
     out = []
-    for launch in [(4, 2), (4, 5), (8, 40)]:
+    for launch in [(4, 2, 1), (4, 5, 1), (8, 40, 1), (4, 3, 2)]:
         lat, _ = make_pair(sc, 40, R=8.0, A=A, steps=20)
         lat.set_launch(*launch)
         lat.set_gradient_table(np.tile(A, (20, 1)), 0)
         lat.step(20)
         out.append(lat.save())
-    assert np.array_equal(out[0][64:], out[1][64:]) and np.array_equal(out[0][64:], out[2][64:])
+    assert all(np.array_equal(out[0][64:], o[64:]) for o in out[1:])
 
 
 def test_periodic_conservation_fp64(sc):
