@@ -80,19 +80,6 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
 // wref (1 + d); any consistent reciprocal will do.
 __device__ __forceinline__ float rel_dev(float v, float wref) { return (v - wref) * __builtin_amdgcn_rcpf(wref); }
 
-// Lane l of a wavefront receives lane l - CX's value (CX = +1 or -1): the DPP
-// whole-wave shift by one lane (wave_shr:1 / wave_shl:1 of the gfx9 family).  The
-// lane that has no source keeps 0.  Every lane of the wave must be active.
-template <int CX>
-__device__ __forceinline__ uint32_t lane_shift(uint32_t v) {
-    static_assert(CX == 1 || CX == -1, "one-lane shifts only");
-    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CX > 0 ? 0x138 : 0x130, 0xf, 0xf, false));
-}
-template <int CX>
-__device__ __forceinline__ uint64_t lane_shift(uint64_t v) {
-    return uint64_t(lane_shift<CX>(uint32_t(v))) | (uint64_t(lane_shift<CX>(uint32_t(v >> 32))) << 32);
-}
-
 template <int P>
 struct Prec;
 template <>
@@ -107,6 +94,11 @@ struct Prec<SCLBM_F64> {
         return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
     }
     using B = uint64_t;  // stored bits
+    using L = uint64_t;  // raw loaded word
+    static __device__ __forceinline__ L bload_raw(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    static __device__ __forceinline__ W dec(L raw, R /*wref*/) { return __builtin_bit_cast(double, raw); }
     static __device__ __forceinline__ B enc(R v, R /*wref*/) { return __builtin_bit_cast(uint64_t, v); }
     static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, b), r, vo, so, 0);
@@ -127,6 +119,11 @@ struct Prec<SCLBM_F32> {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
     }
     using B = uint32_t;
+    using L = uint32_t;
+    static __device__ __forceinline__ L bload_raw(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0);
+    }
+    static __device__ __forceinline__ W dec(L raw, R /*wref*/) { return __builtin_bit_cast(float, raw); }
     static __device__ __forceinline__ B enc(R v, R /*wref*/) { return __builtin_bit_cast(uint32_t, float(v)); }
     static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
         __builtin_amdgcn_raw_buffer_store_b32(b, r, vo, so, 0);
@@ -148,6 +145,13 @@ struct Prec<SCLBM_F16DEV> {
         return wref + wref * __half2float(__builtin_bit_cast(__half, b));
     }
     using B = uint32_t;  // the 16 stored bits in the low half
+    using L = unsigned short;
+    static __device__ __forceinline__ L bload_raw(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+    }
+    static __device__ __forceinline__ W dec(L raw, R wref) {
+        return wref + wref * __half2float(__builtin_bit_cast(__half, raw));
+    }
     static __device__ __forceinline__ B enc(R v, R wref) {
         return __builtin_bit_cast(unsigned short, __float2half_rn(rel_dev(v, wref)));
     }
@@ -171,6 +175,13 @@ struct Prec<SCLBM_BF16DEV> {
         return wref + wref * __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
     }
     using B = uint32_t;
+    using L = unsigned short;
+    static __device__ __forceinline__ L bload_raw(rsrc_t r, uint32_t vo, uint32_t so) {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
+    }
+    static __device__ __forceinline__ W dec(L raw, R wref) {
+        return wref + wref * __bfloat162float(__builtin_bit_cast(__hip_bfloat16, raw));
+    }
     static __device__ __forceinline__ B enc(R v, R wref) {
         return __builtin_bit_cast(unsigned short, __float2bfloat16(rel_dev(v, wref)));
     }

@@ -85,10 +85,10 @@ __device__ __forceinline__ void eq_pair(R cu, R aa, R rho3, R rho45, R &plus, R 
     minus = sym - asym;
 }
 
-// The ten directions with c_x != 0 and their slots in the deferred-store arrays:
-// odd directions have c_x = +1, even ones c_x = -1.
-__host__ __device__ constexpr int xdir_of(int j) { return j < 2 ? j + 1 : j + 5; }
+// The ten directions with c_x != 0 have slots j = 0..9 in the x-exchange
+// buffer (odd directions c_x = +1, even ones -1).
 constexpr int NXD = 10;
+__host__ __device__ constexpr int xslot_of(int i) { return i < 3 ? i - 1 : i - 5; }
 
 template <int P, int TY, int WX, bool GHOST, int WAVES>
 __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
@@ -96,14 +96,19 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     using W = typename Prec<P>::W;
     using R = typename Prec<P>::R;
     using B = typename Prec<P>::B;
+    using L = typename Prec<P>::L;
     using C = R;  // collision arithmetic
     constexpr int TXW = 64 * WX;  // tile width: WX wavefronts per row
     constexpr int LW = TXW + 2;   // with the ring
     constexpr uint32_t EB = sizeof(S);
+    // the next plane's populations are loaded while the current one collides;
+    // FP64 windows leave no registers for a third plane
+    constexpr bool PREFETCH = sizeof(S) < 8;
     __shared__ R lds[4][2][TY + 2][LW];
-    // values that cross a wavefront edge in x, by plane parity, component, c_x != 0
-    // direction, row and wave boundary b (b = 0: the tile's left edge; b = WX: right)
-    __shared__ B edge[2][2][NXD][TY][WX + 1];
+    // x exchange: post-collision values with c_x != 0, by component, slot, row and
+    // column lx + 1; columns 0 and tw + 1 hold what streams in across the tile's
+    // left and right edges (ghost populations, or the periodic wrap)
+    __shared__ B xq[2][NXD][TY][LW];
 
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = ly * TXW + lx;
@@ -126,8 +131,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     const bool valid = (x < a.nx) && (y < a.ny);
     const int tw = min(TXW, a.nx - x0), th = min(TY, a.ny - y0);  // valid tile extent
     const int nw = (tw + 63) >> 6;                                 // wavefronts per row holding nodes
-    const int wlast = min(63, tw - 1 - 64 * wv);                   // this wave's last lane in the box
-    const bool wave_on = (y < a.ny) && (wv < nw);                  // uniform over the wavefront
     const bool left_face = x0 == 0, right_face = x0 + tw == a.nx;
     const bool span = left_face && right_face;                     // the tile holds whole rows
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -150,73 +153,49 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     const __half *ref_in = DEV ? a.ref_src + (int64_t)box * 2 * N : nullptr;
     __half *ref_out = DEV ? a.ref_dst + (int64_t)box * 2 * N : nullptr;
     const R rhob[2] = {R(a.rho_b[0]), R(a.rho_b[1])};
+    // velocity gradient of step n (ghost mode), read before the first store so
+    // that the reads are uniform scalar loads (no wait on the vector-memory queue)
+    R Am[9];
+    if (GHOST) {
+        const double *Arow = a.atab + ((int64_t)box * a.table_len + (n - a.tab_first[box])) * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) Am[q] = R(Arow[q]);
+    }
 
     static_assert(2 * (TXW + 2) + 2 * TY <= TXW * TY, "one ring node per thread");
     const int ringN = 2 * (tw + 2) + 2 * th;
     const int nplanes = (ze - zs) + 2;
 
-    // Stores of the c_x != 0 populations of the plane collided one iteration
-    // earlier (plane zp, edge parity par).  Lane l writes its own node's slot with
-    // the value of lane l - c_x (a whole-wave lane shift), so that every store of a
-    // wavefront covers 64 aligned, consecutive elements and writes whole cache lines;
-    // the lane whose source lies in the next wavefront takes it from LDS, and at an
-    // x face the ghost population put there in its place.  A tile that does not hold
-    // whole rows also writes the one value that leaves it, from its edge lane.
-    B pend[2][NXD];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int j = 0; j < NXD; ++j) pend[s][j] = B(0);
-    auto flush = [&](int zp, int par) {
-        if (!wave_on) return;
-#pragma unroll
-        for (int j = 0; j < NXD; ++j) {
-            const int i = xdir_of(j);
-            const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-            int yd = y + cy, zd = zp + cz;
-            bool out = false;
-            if (GHOST) {
-                out = yd < 0 || yd >= ny || zd < 0 || zd >= nz;
-            } else {
-                yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
-                zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
-            }
-            const uint32_t row = (uint32_t(zd) * uint32_t(ny) + uint32_t(yd)) * qnx + uint32_t(i) * uint32_t(nx);
-            // receiving lane, its source and whether it is written here
-            bool ok = lane <= wlast && !out;
-            int b = 0;
-            bool from_edge = false;
-            if (cx > 0 && lane == 0) {
-                from_edge = true;
-                if (wv > 0) b = wv;
-                else if (GHOST) { b = 0; ok = ok && left_face; }
-                else { b = nw; ok = ok && span; }
-            }
-            if (cx < 0 && lane == wlast) {
-                from_edge = true;
-                if (wv < nw - 1) b = wv + 1;
-                else if (GHOST) { b = nw; ok = ok && right_face; }
-                else { b = 0; ok = ok && span; }
-            }
+    // own node of plane z: whether it is inside the box (ghost mode), its
+    // population byte offset and node index (periodic mode wraps z)
+    auto own_node = [&](int z, uint32_t &vo, uint32_t &nd) -> bool {
+        int zz = z;
+        bool in = (z >= 0) && (z < nz);
+        if (!GHOST) {
+            zz = z < 0 ? z + nz : (z >= nz ? z - nz : z);
+            in = true;
+        }
+        vo = ((uint32_t(zz) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(x)) * EB;
+        nd = uint32_t(zz) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
+        return in && valid;
+    };
+    // raw words of the next plane and, for the deviation formats, its reference densities
+    L fnx[2][Q];
+    R rnx[2] = {R(0), R(0)};
+    bool nx_in = false;
+    auto prefetch = [&](int z) {
+        uint32_t vo, nd;
+        nx_in = own_node(z, vo, nd);
+        if (nx_in) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                const B sh = cx > 0 ? lane_shift<1>(pend[s][j]) : lane_shift<-1>(pend[s][j]);
-                const B v = from_edge ? edge[par][s][j][ly][b] : sh;
-                Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0, v);
-            }
-            if (!span) {
-                // the value that leaves the tile: c_x = +1 from the last lane, -1 from lane 0
-                const bool src_lane = cx > 0 ? (lane == wlast && wv == nw - 1) : (lane == 0 && wv == 0);
-                int xd = cx > 0 ? x0 + tw : x0 - 1;
-                bool go = src_lane && !out;
-                if (GHOST) go = go && (cx > 0 ? !right_face : !left_face);
-                else xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+                if (DEV) rnx[s] = R(ref_load(ref_in + s * N + nd));
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
-                    Prec<P>::bstore_bits(rd[s], go ? (row + uint32_t(xd)) * EB : kOOB, 0, pend[s][j]);
+                for (int i = 0; i < Q; ++i) fnx[s][i] = Prec<P>::bload_raw(rs[s], vo, uint32_t(i) * plane_bytes);
             }
         }
     };
+    if (PREFETCH) prefetch(zs - 1);
 
     W fprev[2][Q], fcur[2][Q];
     for (int k = 0; k < nplanes; ++k) {
@@ -224,19 +203,31 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         const int slot = k & 3;
         // ---- 1. densities of plane z: own node (into the register window) and one
         // ring node per thread ----
-        bool own_in = false, ring_on = false, ring_in = false;
-        uint32_t own_vo = 0, ring_vo = 0, own_nd = 0, ring_nd = 0;  // population byte offsets, node indices
-        int rsx = 0, rsy = 0;
-        if (valid) {
-            int zz = z;
-            own_in = (z >= 0) && (z < nz);
-            if (!GHOST) {
-                zz = z < 0 ? z + nz : (z >= nz ? z - nz : z);
-                own_in = true;
+        bool own_in;
+        if (PREFETCH) {
+            own_in = nx_in;
+            if (own_in) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) fcur[s][i] = Prec<P>::dec(fnx[s][i], w_of<R>(i) * rnx[s]);
             }
-            own_vo = ((uint32_t(zz) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(x)) * EB;
-            own_nd = uint32_t(zz) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
+        } else {
+            uint32_t own_vo, own_nd;
+            own_in = own_node(z, own_vo, own_nd);
+            if (own_in) {
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const R rr = DEV ? R(ref_load(ref_in + s * N + own_nd)) : R(0);
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                        fcur[s][i] = Prec<P>::bload(rs[s], own_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rr);
+                }
+            }
         }
+        bool ring_on = false, ring_in = false;
+        uint32_t ring_vo = 0, ring_nd = 0;
+        int rsx = 0, rsy = 0;
         if (tid < ringN) {
             const int r = tid;
             if (r < tw + 2) {
@@ -264,15 +255,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             ring_vo = ((uint32_t(gz) * uint32_t(ny) + uint32_t(gy)) * qnx + uint32_t(gx)) * EB;
             ring_nd = uint32_t(gz) * nxy + uint32_t(gy) * uint32_t(nx) + uint32_t(gx);
         }
-        if (own_in) {
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const R rr = DEV ? R(ref_load(ref_in + s * N + own_nd)) : R(0);
-#pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    fcur[s][i] = Prec<P>::bload(rs[s], own_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rr);
-            }
-        }
         if (valid) {
             const R r0 = own_in ? pair_density<R>(fcur[0]) : rhob[0];
             const R r1 = own_in ? pair_density<R>(fcur[1]) : rhob[1];
@@ -296,18 +278,16 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             lds[slot][1][rsy][rsx] = rr[1];
         }
         __syncthreads();
-        // ---- 2. the c_x != 0 stores of the plane collided one iteration ago (their
-        // edge values are visible after the barrier) ----
-        if (k >= 3) flush(z - 2, (k - 1) & 1);
+        // ---- 2. the next plane's loads go out now and land during the collision ----
+        if (PREFETCH && k + 1 < nplanes) prefetch(z + 1);
         if (k >= 2) {
-        // ---- 3. collide plane z-1: c_x = 0 populations are stored now, the others
-        // after the next barrier ----
+        // ---- 3. collide plane z-1: c_x = 0 populations are pushed now, the others
+        // go through LDS ----
         const int zc = z - 1;
-        const int par = k & 1;
         const uint32_t node = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
         const uint32_t elem = (uint32_t(zc) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(x);
         const uint32_t vo = elem * EB;
-        const bool xlo = x == 0, xhi = x == nx - 1, ylo = y == 0, yhi = y == ny - 1;
+        const bool ylo = y == 0, yhi = y == ny - 1;
         const bool zlo = zc == 0, zhi = zc == nz - 1;
         if (valid) {
             const W (&f)[2][Q] = fprev;  // populations of plane z-1, loaded one plane ago
@@ -378,10 +358,12 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                                        : C(0);
                     const B bits = Prec<P>::enc(pst, w_of<C>(i) * dref);
                     if (cx_of(i) != 0) {
-                        const int jx = i < 3 ? i - 1 : i - 5;
-                        pend[s][jx] = bits;
-                        if (cx_of(i) > 0 && lane == wlast) edge[par][s][jx][ly][wv + 1] = bits;
-                        if (cx_of(i) < 0 && lane == 0) edge[par][s][jx][ly][wv] = bits;
+                        xq[s][xslot_of(i)][ly][lx + 1] = bits;
+                        // periodic rows held whole: the wrap across the box's x faces
+                        if (!GHOST && span) {
+                            if (cx_of(i) > 0 && lx == tw - 1) xq[s][xslot_of(i)][ly][0] = bits;
+                            if (cx_of(i) < 0 && lx == 0) xq[s][xslot_of(i)][ly][tw + 1] = bits;
+                        }
                         return;
                     }
                     uint32_t dvo;
@@ -415,19 +397,14 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 push(0, aa);
             }
         }
-        if (GHOST && wave_on) {
+        if (GHOST && y < ny) {
             // Populations streaming in from ghost nodes, which hold
             // g_eq(rho_b, A (x_g - x_c)).
-            const double *Arow = a.atab + ((int64_t)box * a.table_len + (n - a.tab_first[box])) * 9;
-            R Am[9];  // read once: the stores below may alias the table as far as the compiler knows
-#pragma unroll
-            for (int q = 0; q < 9; ++q) Am[q] = R(__builtin_nontemporal_load(Arow + q));
             // (a) Ghosts beside this row at x = -1 and x = nx: their five populations
             // with c_x pointing into the box stream into the face nodes of the rows
-            // y + c_y, z + c_z; they take the place, in the deferred stores, of the
-            // value a left or right neighbour would have pushed.  Lanes 0-9 of the
-            // first wavefront do the left side, lanes 16-25 of the last the right,
-            // lane 2m + s taking incoming direction m of component s.
+            // y + c_y, z + c_z, and enter the x exchange at the tile's edge columns.
+            // Lanes 0-9 of the first wavefront do the left side, lanes 16-25 of the
+            // last the right, lane 2m + s taking incoming direction m of component s.
             const int side = lane < 16 ? 0 : 1;
             const int q = lane - 16 * side;
             if (q < 10 && (side ? (right_face && wv == nw - 1) : (left_face && wv == 0))) {
@@ -449,8 +426,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
                 // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
                 const R fref = DEV ? R(ref_round(float(lds[(k - 1 + czv) & 3][s][ly + 1 + cyv][fx - x0 + 1]))) : R(0);
-                const int jx = idx < 3 ? idx - 1 : idx - 5;
-                edge[par][s][jx][ly][side ? nw : 0] = Prec<P>::enc(geq, wgt * fref);
+                xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = Prec<P>::enc(geq, wgt * fref);
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
             // the directions whose source lies outside the box in y or z, edges
@@ -479,16 +455,52 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 }
             }
         }
+        __syncthreads();
+        // ---- 4. the c_x != 0 stores: lane x writes its own slot with the value
+        // pushed from x - c_x, so that every store of a wavefront covers 64 aligned
+        // consecutive elements (whole cache lines).  A tile that does not hold whole
+        // rows also writes the one value that leaves it across each edge.
+        if (valid) {
+#pragma unroll
+            for (int jx = 0; jx < NXD; ++jx) {
+                const int i = jx < 2 ? jx + 1 : jx + 5;
+                const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+                int yd = y + cy, zd = zc + cz;
+                bool out = false;
+                if (GHOST) {
+                    out = yd < 0 || yd >= ny || zd < 0 || zd >= nz;
+                } else {
+                    yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+                    zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
+                }
+                const uint32_t row = (uint32_t(zd) * uint32_t(ny) + uint32_t(yd)) * qnx + uint32_t(i) * uint32_t(nx);
+                bool ok = !out;
+                if (cx > 0 && lx == 0) ok = ok && (GHOST ? left_face : span);
+                if (cx < 0 && lx == tw - 1) ok = ok && (GHOST ? right_face : span);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0, xq[s][jx][ly][lx + 1 - cx]);
+                if (!span) {
+                    const bool edge = cx > 0 ? lx == tw - 1 : lx == 0;
+                    int xd = x + cx;
+                    bool go = edge && !out;
+                    if (GHOST) go = go && (cx > 0 ? !right_face : !left_face);
+                    else xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+                    if (go) {
+#pragma unroll
+                        for (int s = 0; s < 2; ++s)
+                            Prec<P>::bstore_bits(rd[s], (row + uint32_t(xd)) * EB, 0, xq[s][jx][ly][lx + 1]);
+                    }
+                }
+            }
+        }
         }  // k >= 2
-        // ---- 4. roll the register window ----
+        // ---- 5. roll the register window ----
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int i = 0; i < Q; ++i) fprev[s][i] = fcur[s][i];
     }
-    // the last collided plane's deferred stores
-    __syncthreads();
-    flush(ze - 1, (nplanes - 1) & 1);
 }
 
 }  // namespace sclbm
