@@ -101,9 +101,11 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     constexpr int TXW = 64 * WX;  // tile width: WX wavefronts per row
     constexpr int LW = TXW + 2;   // with the ring
     constexpr uint32_t EB = sizeof(S);
-    // the next plane's populations are loaded while the current one collides;
-    // FP64 windows leave no registers for a third plane
-    constexpr bool PREFETCH = sizeof(S) < 8;
+    // the next plane's populations are loaded while the current one collides
+    // (FP32 storage: HBM-bound).  FP64 windows leave no registers for a third
+    // plane; the 16-bit formats are bound by instruction issue, and the third
+    // window measured 4 % slower there.
+    constexpr bool PREFETCH = sizeof(S) == 4;
     __shared__ R lds[4][2][TY + 2][LW];
     // x exchange: post-collision values with c_x != 0, by component, slot, row and
     // column lx + 1; columns 0 and tw + 1 hold what streams in across the tile's

@@ -116,6 +116,30 @@ def test_launch_shape_does_not_change_bits(sc):
     assert all(np.array_equal(out[0][64:], o[64:]) for o in out[1:])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16dev", "bf16dev"])
+@pytest.mark.parametrize("bc,nx", [("ghost", 100), ("ghost", 150), ("periodic", 150)])
+def test_launch_shape_bits_every_format(sc, prec, bc, nx):
+    """Every storage format gives the same bits at every tile shape: one-wavefront
+    tiles (values cross between workgroups at every 64 nodes), a 128-wide tile
+    holding whole rows with a partial second wavefront (nx = 100), and a 128-wide
+    tile plus a 22-wide one (nx = 150).  The x-shifted populations go through
+    the LDS exchange in all of them; a wrong edge column or a lost cross-tile
+    value would show as a bit difference."""
+    A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
+    steps = 12
+    out = []
+    for launch in [(8, 4, 1), (4, 3, 2), (4, 100, 1)]:
+        lat, _ = make_pair(sc, None, nxyz=(nx, 10, 9), prec=prec, bc=bc, R=4.0, A=A if bc == "ghost" else None,
+                           steps=steps)
+        lat.set_launch(*launch)
+        if bc == "ghost":
+            lat.set_gradient_table(np.tile(A, (steps, 1)), 0)
+        lat.step(steps)
+        out.append(lat.save())
+        lat.close()
+    assert all(np.array_equal(out[0][64:], o[64:]) for o in out[1:])
+
+
 def test_periodic_conservation_fp64(sc):
     n = 48
     lat, _ = make_pair(sc, n, bc="periodic", R=10.0)
