@@ -232,7 +232,8 @@ sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t 
 /* Autotuner: time trial_steps steps (after one warm-up step) for every tile
  * shape ((4, 1), (8, 1), and (4, 2) when nx > 64) and z-chunk (2, 4, 8, 16,
  * 32, 64, capped at nz), keep the fastest and set it.  The output pointers
- * (may be NULL) receive its shape and the best average step time in ms.  The trials overwrite the populations (call it before an init call, or
+ * (may be NULL) receive its shape and the best average step time in ms.
+ * The trials overwrite the populations (call it before an init call, or
  * re-initialise after) but restore the time.  In ghost mode every box's table
  * must cover steps n .. n + trial_steps.  Synchronises. */
 sclbm_status sclbm_autotune(sclbm_ctx *ctx, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk,

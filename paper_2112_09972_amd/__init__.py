@@ -500,6 +500,9 @@ class Lattice:
         sclbm_load(self.ctx, np.ascontiguousarray(buf))
 
     def set_launch(self, tile_rows, zchunk, tile_waves=1):
+        """Step-kernel tile of tile_rows rows x tile_waves 64-node wavefronts and
+        z-chunk of zchunk planes; (tile_rows, tile_waves) in (4, 1), (8, 1), (4, 2).
+        Speed only: results are bitwise the same for every shape."""
         sclbm_set_launch(self.ctx, tile_rows, zchunk, tile_waves)
 
     def get_launch(self):
