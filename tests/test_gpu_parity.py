@@ -196,6 +196,12 @@ def test_step_past_table_and_mach_errors(sc):
     with pytest.raises(sc.SclbmError) as ei:
         lat.set_gradient_table(np.tile(wl.simple_shear(0.05), (10, 1)), 10)
     assert ei.value.status == sc.SCLBM_EINVAL and "ghost speed" in str(ei.value)
+    # tile shapes outside (4, 1), (8, 1), (4, 2) and z-chunks below 1 are refused
+    for bad in [(2, 16, 2), (8, 16, 2), (4, 16, 3), (6, 16, 1), (4, 0, 1)]:
+        with pytest.raises(sc.SclbmError) as ei:
+            lat.set_launch(*bad)
+        assert ei.value.status == sc.SCLBM_EINVAL
+    assert lat.get_launch()[0] in (4, 8)
 
 
 def test_full_size_128_fp32_all_nodes(sc):
