@@ -108,11 +108,10 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     constexpr int TXW = 64 * WX;  // tile width: WX wavefronts per row
     constexpr int LW = TXW + 2;   // with the ring
     constexpr uint32_t EB = sizeof(S);
-    // the next plane's populations are loaded while the current one collides
-    // (FP32 storage: HBM-bound).  FP64 windows leave no registers for a third
-    // plane; the 16-bit formats are bound by instruction issue, and the third
-    // window measured 4 % slower there.
-    constexpr bool PREFETCH = sizeof(S) == 4;
+    // the next plane's populations (raw words, decoded when the plane is used, so
+    // that nothing waits for them during the collision) are loaded while the
+    // current one collides.  FP64 windows leave no registers for a third plane.
+    constexpr bool PREFETCH = sizeof(S) < 8;
     __shared__ R lds[4][2][TY + 2][LW];
     // x exchange: post-collision values with c_x != 0, by component, slot, row and
     // column lx + 1; columns 0 and tw + 1 hold what streams in across the tile's
@@ -190,7 +189,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     };
     // raw words of the next plane and, for the deviation formats, its reference densities
     L fnx[2][Q];
-    R rnx[2] = {R(0), R(0)};
+    __half rnx[2] = {__half(0.0f), __half(0.0f)};
     bool nx_in = false;
     auto prefetch = [&](int z) {
         uint32_t vo, nd;
@@ -198,7 +197,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         if (nx_in) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                if (DEV) rnx[s] = R(ref_load(ref_in + s * N + nd));
+                if (DEV) rnx[s] = ref_in[s * N + nd];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) fnx[s][i] = Prec<P>::bload_raw(rs[s], vo, uint32_t(i) * plane_bytes);
             }
@@ -219,7 +218,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) fcur[s][i] = Prec<P>::dec(fnx[s][i], w_of<R>(i) * rnx[s]);
+                    for (int i = 0; i < Q; ++i) fcur[s][i] = Prec<P>::dec(fnx[s][i], w_of<R>(i) * R(__half2float(rnx[s])));
             }
         } else {
             uint32_t own_vo, own_nd;
