@@ -501,6 +501,16 @@ StepArgs base_args(sclbm_ctx *c) {
     a.nz = c->cfg.nz;
     a.zchunk = c->zchunk;
     a.nzc = (c->cfg.nz + c->zchunk - 1) / c->zchunk;
+    // z-chunks grouped in the tile order: the largest divisor of nzc with
+    // (x tiles) x (group) <= 4 (measured best or within 0.5 % on the 128^3 and
+    // 256^3 boxes, against y-major order and larger groups)
+    {
+        const int ntx = (c->cfg.nx + 64 * c->tile_waves - 1) / (64 * c->tile_waves);
+        int g = 1;
+        for (int d = 1; d <= a.nzc && d * ntx <= 4; ++d)
+            if (a.nzc % d == 0) g = d;
+        a.zgroup = g;
+    }
     for (int s = 0; s < 2; ++s) {
         a.tau[s] = c->cfg.tau[s];
         a.omega[s] = 1.0 / c->cfg.tau[s];

@@ -16,11 +16,12 @@
 //
 // Tiling.  A workgroup owns a tile of TY rows of WX wavefronts (64 WX x TY nodes
 // in (x, y); 128 x 4 holds whole rows of a 128-wide box) and marches along z
-// through a chunk of planes.  The force at plane z needs the densities of planes
+// through a chunk of planes (up in even chunks, down in odd ones).  The force at
+// plane z needs the densities of planes
 // z-1, z, z+1 including a one-node ring around the tile; those densities live in
 // a 4-slot rolling buffer in LDS.  Per plane each thread takes its node's 38
-// populations into a register window (FP32 storage: loaded during the previous
-// plane's collision) and sums them into densities, the workgroup adds the ring
+// populations into a register window (FP32 and 16-bit storage: loaded during the
+// previous plane's collision) and sums them into densities, the workgroup adds the ring
 // densities, and after a barrier the previous plane's window is collided.
 // Ring densities (and the two chunk-end planes) are recomputed rather than
 // exchanged between workgroups, so a step is a single launch with no grid-wide
@@ -58,6 +59,7 @@ struct StepArgs {
     int64_t table_len;
     int64_t nnode;            // nodes per box
     int nx, ny, nz, nzc, zchunk;
+    int zgroup;               // z-chunks that follow one another in the tile order (divides nzc)
     double omega[2];          // 1/tau
     double tau[2];
     double g;                 // G_AB
@@ -122,15 +124,26 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     const int tid = ly * TXW + lx;
     const int lane = lx & 63, wv = lx >> 6;
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8
-    // XCDs by linear id, so give XCD k one contiguous run of tiles (x fastest,
-    // then y, then z-chunk and box).  Neighbouring tiles then share an L2 for
-    // their ring re-reads.
+    // XCDs by linear id, so give XCD k one contiguous run of tiles, ordered x
+    // fastest, then a group of zgroup z-chunks, then y, then the chunk groups,
+    // then box.  Tiles that run at the same time on one XCD then cover a block
+    // of neighbouring rows and chunks: ring rows and, since even chunks march up
+    // in z and odd ones down, the planes at a chunk boundary inside the group are
+    // read by two tiles at about the same time and the second read hits in L2.
     const uint32_t nbx = gridDim.x, nby = gridDim.y;
     const uint32_t nb = nbx * nby * gridDim.z;
     const uint32_t lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
     const uint32_t q8 = nb / 8, r8 = nb % 8, xcd = lin % 8, k8 = lin / 8;
     const uint32_t tile = xcd < r8 ? xcd * (q8 + 1) + k8 : r8 * (q8 + 1) + (xcd - r8) * q8 + k8;
-    const int bx = int(tile % nbx), by = int((tile / nbx) % nby), bz = int(tile / (nbx * nby));
+    const int bx = int(tile % nbx);
+    uint32_t t2 = tile / nbx;
+    const uint32_t zg = uint32_t(a.zgroup), ngr = uint32_t(a.nzc) / zg;
+    const uint32_t ci = t2 % zg;
+    t2 /= zg;
+    const int by = int(t2 % nby);
+    t2 /= nby;
+    const int chunk = int((t2 % ngr) * zg + ci);
+    const int bz = int(t2 / ngr) * a.nzc + chunk;
     const int x0 = bx * TXW, y0 = by * TY;
     const int box = bz / a.nzc;
     const int zs = (bz % a.nzc) * a.zchunk;
@@ -203,11 +216,13 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             }
         }
     };
-    if (PREFETCH) prefetch(zs - 1);
+    const int dir = (chunk & 1) ? -1 : 1;  // march direction in z
+    const int zfirst = dir > 0 ? zs - 1 : ze;
+    if (PREFETCH) prefetch(zfirst);
 
     W fprev[2][Q], fcur[2][Q];
     for (int k = 0; k < nplanes; ++k) {
-        const int z = zs - 1 + k;
+        const int z = zfirst + dir * k;
         const int slot = k & 3;
         // ---- 1. densities of plane z: own node (into the register window) and one
         // ring node per thread ----
@@ -287,18 +302,19 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         }
         __syncthreads();
         // ---- 2. the next plane's loads go out now and land during the collision ----
-        if (PREFETCH && k + 1 < nplanes) prefetch(z + 1);
+        if (PREFETCH && k + 1 < nplanes) prefetch(z + dir);
         if (k >= 2) {
-        // ---- 3. collide plane z-1: c_x = 0 populations are pushed now, the others
-        // go through LDS ----
-        const int zc = z - 1;
+        // ---- 3. collide the previous plane of the march, zc = z - dir: c_x = 0
+        // populations are pushed now, the others go through LDS ----
+        const int zc = z - dir;  // plane zc + d sits in LDS slot sl(d)
+        auto sl = [&](int d) { return (k - 1 + dir * d) & 3; };
         const uint32_t node = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
         const uint32_t elem = (uint32_t(zc) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(x);
         const uint32_t vo = elem * EB;
         const bool ylo = y == 0, yhi = y == ny - 1;
         const bool zlo = zc == 0, zhi = zc == nz - 1;
         if (valid) {
-            const W (&f)[2][Q] = fprev;  // populations of plane z-1, loaded one plane ago
+            const W (&f)[2][Q] = fprev;  // populations of plane zc, loaded one plane ago
             // moments, Eq. 6: density and momentum from pair sums and differences
             R rho[2], j[2][3];
 #pragma unroll
@@ -321,8 +337,8 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
 #pragma unroll
                 for (int p = 1; p <= 9; ++p) {
                     const int i = 2 * p - 1;
-                    const R hi = lds[(k - 1 + cz_of(i)) & 3][o][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)];
-                    const R lo = lds[(k - 1 - cz_of(i)) & 3][o][ly + 1 - cy_of(i)][lx + 1 - cx_of(i)];
+                    const R hi = lds[sl(cz_of(i))][o][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)];
+                    const R lo = lds[sl(-cz_of(i))][o][ly + 1 - cy_of(i)][lx + 1 - cx_of(i)];
                     e[p] = hi - lo;
                 }
                 const R w1 = R(1) / R(18), w2 = R(1) / R(36);
@@ -362,7 +378,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     }
                     // deviation formats: relative to the destination's density at time n,
                     // rounded as the destination's own thread stores it below
-                    const C dref = DEV ? C(ref_round(float(lds[(k - 1 + cz_of(i)) & 3][s][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)])))
+                    const C dref = DEV ? C(ref_round(float(lds[sl(cz_of(i))][s][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)])))
                                        : C(0);
                     const B bits = Prec<P>::enc(pst, w_of<C>(i) * dref);
                     if (cx_of(i) != 0) {
@@ -433,7 +449,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
                 const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
                 // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
-                const R fref = DEV ? R(ref_round(float(lds[(k - 1 + czv) & 3][s][ly + 1 + cyv][fx - x0 + 1]))) : R(0);
+                const R fref = DEV ? R(ref_round(float(lds[sl(czv)][s][ly + 1 + cyv][fx - x0 + 1]))) : R(0);
                 xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = Prec<P>::enc(geq, wgt * fref);
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
@@ -457,7 +473,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     const R wgt = i < 7 ? R(1) / R(18) : R(1) / R(36);
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
-                        const R oref = DEV ? R(ref_round(float(lds[(k - 1) & 3][s][ly + 1][lx + 1]))) : R(0);
+                        const R oref = DEV ? R(ref_round(float(lds[sl(0)][s][ly + 1][lx + 1]))) : R(0);
                         Prec<P>::bstore(rd[s], vo + uint32_t(i) * plane_bytes, 0, wgt * rhob[s] * br, wgt * oref);
                     }
                 }
