@@ -65,6 +65,10 @@ def _load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsclbm.so is not built (%s); run `python -c \"import __graft_entry__ as g; g.build()\"`"
                           % LIB_PATH)
+    # PyTorch brings its own HIP runtime.  Loading it first makes the library bind
+    # to that same runtime; loaded the other way round the process holds two HIP
+    # and two HSA runtimes, and the library's one finds no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     I32, I64, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double

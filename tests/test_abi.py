@@ -25,14 +25,27 @@ def header_functions():
 
 
 def test_library_exports_every_declared_call():
-    import ctypes
     import paper_2112_09972_amd as sc
-    lib = ctypes.CDLL(sc.LIB_PATH)
+    lib = sc.load()                     # the package's loader (one HIP runtime per process)
     names = header_functions()
     assert len(names) >= 38
     for name in names:
         assert hasattr(lib, name), name
     assert sorted(sc.EXPORTS) == names
+
+
+def test_library_shares_torch_hip_runtime():
+    """Loading the library makes it bind to PyTorch's HIP runtime: the process
+    then maps a single HIP runtime, whatever was imported first (two runtimes in
+    one process leave the library without a device)."""
+    import subprocess
+    import sys
+    code = ("import paper_2112_09972_amd as sc; sc.load(); "
+            "maps = open('/proc/self/maps').read(); "
+            "print(len({l.split()[-1] for l in maps.splitlines() if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
 
 
 def cfg(**kw):
