@@ -539,7 +539,7 @@ hipError_t enqueue_steps(sclbm_ctx *c, int64_t nsteps, int par) {
 }
 
 void drop_graph(sclbm_ctx *c) {
-    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     c->graph_exec = nullptr;
     c->graph_steps = 0;
     c->graph_par = -1;
@@ -573,11 +573,11 @@ sclbm_status sclbm_step_graph(sclbm_ctx *c, int64_t nsteps) {
         hipError_t e = enqueue_steps(c, nsteps, c->par);
         hipError_t e2 = hipStreamEndCapture(c->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
             return fail(SCLBM_EHIP, "graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
         }
         e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
             c->graph_exec = nullptr;
             return fail(SCLBM_EHIP, "graph instantiate: %s", hipGetErrorString(e));
@@ -639,8 +639,8 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
                 bzc = c->zchunk;
             }
         }
-    hipEventDestroy(ev0);
-    hipEventDestroy(ev1);
+    (void)hipEventDestroy(ev0);  // teardown: nothing to do on failure
+    (void)hipEventDestroy(ev1);
     // restore the time; the populations hold trial results
     int64_t clk[2] = {n0, n0};
     HIP_TRY(hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream));
