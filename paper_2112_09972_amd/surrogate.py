@@ -307,18 +307,22 @@ def errors(pred: np.ndarray, truth: np.ndarray) -> dict:
 
 
 def inference_seconds(net: Network, batch: int = 8192, reps: int = 20, device="cuda:0", windows=None) -> float:
-    """Average time of one inference batch, timed with HIP events on the network's stream."""
+    """Average time of one inference batch: back-to-back sclmlp_predict calls
+    through the C ABI on the network's stream, timed with HIP events on that
+    stream (the Network.predict wrapper adds PyTorch stream synchronisation on
+    the host around each call)."""
     import torch
+    from .mlp import sclmlp_predict
     if windows is None:
         windows = np.random.default_rng(0).standard_normal((batch, NIN)).astype(np.float32) * 1e-3
     X = torch.from_numpy(np.ascontiguousarray(windows[:batch], dtype=np.float32)).to(device)
     out = torch.empty((X.shape[0], 3), dtype=torch.float32, device=device)
     net.predict(X, out)
-    net.stream.synchronize()
+    torch.cuda.synchronize(device)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(net.stream)
     for _ in range(reps):
-        net.predict(X, out)
+        sclmlp_predict(net.ctx, X, X.shape[0], out)
     e1.record(net.stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / reps
