@@ -24,13 +24,19 @@ def ou_tables(n, nbox, steps, seed0=1000):
     return [wl.ou_gradient_table(seed0 + b, n, steps, mach=0.1 + 0.05 * b) for b in range(nbox)]
 
 
-def test_ensemble_equals_independent_boxes(sc):
+@pytest.mark.parametrize("launch", [None, (4, 6, 1), (4, 7, 2)])
+def test_ensemble_equals_independent_boxes(sc, launch):
     """Every box of a 3-box ensemble is bit-identical to the same box run alone,
-    and box 1 matches the oracle."""
+    and box 1 matches the oracle; also with four z-chunks per box grouped in the
+    tile order (chunks of 6, and of 7 with a ragged last chunk on 128-wide
+    tiles), marching in alternating directions, where a run of tiles on one
+    XCD spans chunks of several boxes."""
     n, nbox, steps, R = 24, 3, 40, 5.0
     tabs = ou_tables(n, nbox, steps)
     ens = sc.Lattice(n, n, n, nbox=nbox, bc="ghost", prec="f64", table_len=steps, g_ab=wl.G_AB,
                      rho_b=wl.ghost_densities(R))
+    if launch:
+        ens.set_launch(*launch)
     for b in range(nbox):
         ens.init_droplet(ens.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0], box=b)
         ens.set_gradient_table(tabs[b], 0, box=b)
