@@ -17,8 +17,8 @@ The same line carries the surrogate comparison ("surrogate"): the ensemble of
 64 boxes of 64^3 (R = 10, FP32, one OU drive each, 20000 lattice steps through
 the captured step loop, droplet moments every 50 steps) gives the lattice
 Boltzmann rate of shape samples and the training windows; the network is
-trained on 56 trajectories by the library's kernels and judged on the 8 held
-out, and one 8192-window inference batch is timed with HIP events.  Surrogate
+trained on 56 trajectories by the library's kernels and evaluated on the 8
+held out, and one 8192-window inference batch is timed with HIP events.  Surrogate
 samples/s count the lattice Boltzmann replays of windows whose predicted D
 exceeds 0.5.
 """
@@ -204,8 +204,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
-              "(multi-GPU sharding is a design note only); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the hot path on a single MI355X "
+              "(sharding over several GPUs is designed but not built); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

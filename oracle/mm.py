@@ -18,7 +18,7 @@ f1(chi) = 40 (chi + 1) / ((3 + 2 chi)(16 + 19 chi)),
 f2(chi, Ca) = 5 / (3 + 2 chi) + 3 Ca^2 / (2 + 6 Ca^2),
 III_M = det M, II_M = (tr(M)^2 - M:M) / 2.
 
-Integration (this build's reading; the paper does not say): classical RK4
+Integration (a reading: the paper does not say how it integrates): classical RK4
 with `substeps` equal steps per table row, A(t) linear between consecutive rows
 (row n at time n).
 """

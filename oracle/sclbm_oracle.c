@@ -192,7 +192,7 @@ void orc_init_fields(orc_state *s, const double *rho_a, const double *rho_b, con
  * between rho_in (inside) and rho_out (outside); component B is the mirror
  * profile so that rho_A + rho_B = rho_in + rho_out everywhere.  Velocity
  * u = A0 (x - x_c).  The paper only says the droplet sits at the centre of the
- * box; the profile is this build's reading. */
+ * box; the tanh profile is a reading. */
 void orc_init_droplet(orc_state *s, const double *ctr, double radius, double xi, double rho_in,
                       double rho_out, const double *A0 /* 9, row-major, A_ij = d_j u_i */) {
     double *ra = (double *)malloc(s->n * sizeof(double));

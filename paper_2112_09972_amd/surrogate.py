@@ -4,8 +4,8 @@ The paper couples each droplet box to the velocity-gradient history A(t) seen
 by a tracer (Sec. 3) and reads the droplet's shape from the semi-axes of its
 inertia ellipsoid and the deformation D (Sec. 2 Eq. 4).  This module trains a
 network that predicts those semi-axes from a window of recent A(t) samples,
-with the full lattice Boltzmann box as its data source, its judge and its
-fallback:
+with the full lattice Boltzmann box as its data source, its reference and
+its fallback:
 
 1. ``generate``: an ensemble of droplet boxes, each driven by its own A(t),
    runs in one launch per step (step loop replayed from a captured hipGraph,
