@@ -119,7 +119,9 @@ def precision_study(sc, nsteps: int):
         mm = mom.cpu().numpy()
         st = [sc.sclbm_droplet_from_moments(mm[i], lat.xc) for i in range(ns)]
         series[prec] = (np.array([x["semi_axes"] for x in st]), np.array([x["deformation"] for x in st]))
+        ty, zc, wx = lat.get_launch()
         r = {"mlups": round(nodes * STRIDE * ns / el / 1e6, 1), "bytes_per_update": bpl[prec],
+             "launch": {"tile_rows": ty, "zchunk": zc, "tile_waves": wx},
              "mass_drift_rel": [float(v) for v in (m1 - m0) / m0]}
         if prec != "f64":
             a64, d64 = series["f64"]

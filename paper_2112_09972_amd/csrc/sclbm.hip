@@ -16,6 +16,7 @@
 #include "mm_kernel.hpp"
 #include "sclbm.h"
 #include "step_kernel.hpp"
+#include "step_pair_kernel.hpp"
 
 using namespace sclbm;
 
@@ -168,10 +169,23 @@ void default_tile(const sclbm_config &c, int &ty, int &wx) {
     ty = wx == 2 ? 4 : 8;
 }
 
+// Whether a step runs the two-nodes-per-lane kernel (k_step_pair): the 16-bit
+// deviation formats on a 128 x 4 tile with an even nx.
+bool uses_pair_kernel(const sclbm_config &c, int ty, int wx) {
+    return is_dev(c.prec) && ty == 4 && wx == 2 && c.nx % 2 == 0;
+}
+
 // z-chunk so that the grid holds about two resident waves per SIMD
 // (256 CUs x 4 SIMDs x 2 waves = 2048 waves = 2048 / (TY WX) workgroups).
+// The pair kernel (4 wavefronts, 64 KB of LDS per workgroup; 512 resident) runs
+// best with about four rounds of resident workgroups and chunks of at least 8
+// planes (measured on 128^3 and 256^3 boxes: 16 chunks in z in both).
 int default_zchunk(const sclbm_config &c, int ty, int wx) {
     const long tiles = long((c.nx + 64 * wx - 1) / (64 * wx)) * long((c.ny + ty - 1) / ty) * c.nbox;
+    if (uses_pair_kernel(c, ty, wx)) {
+        const long zc = (tiles * c.nz + 2047) / 2048;
+        return int(std::max(std::min(8L, long(c.nz)), std::min(zc, long(c.nz))));
+    }
     const long groups = 2048 / (ty * wx);
     long zc = (tiles * c.nz + groups - 1) / groups;
     zc = std::max(2L, std::min(zc, long(c.nz)));
@@ -192,8 +206,25 @@ hipError_t launch_step_tile(sclbm_ctx *c, const StepArgs &a) {
     return hipGetLastError();
 }
 
+// The 16-bit deviation formats on a 128 x 4 tile with an even nx: one wavefront
+// per row, two nodes per lane (same results, half the memory instructions).
+template <int P>
+hipError_t launch_step_pair(sclbm_ctx *c, const StepArgs &a) {
+    constexpr int TY = 4;
+    dim3 block(64, TY, 1);
+    dim3 grid((c->cfg.nx + 127) / 128, (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
+    if (c->cfg.bc == SCLBM_BC_GHOST)
+        hipLaunchKernelGGL((k_step_pair<P, TY, true>), grid, block, 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_step_pair<P, TY, false>), grid, block, 0, c->stream, a);
+    return hipGetLastError();
+}
+
 template <int P>
 hipError_t launch_step(sclbm_ctx *c, const StepArgs &a) {
+    if constexpr (Prec<P>::DEV) {
+        if (uses_pair_kernel(c->cfg, c->tile_rows, c->tile_waves)) return launch_step_pair<P>(c, a);
+    }
     if (c->tile_waves == 2) return launch_step_tile<P, 4, 2>(c, a);
     if (c->tile_rows == 8) return launch_step_tile<P, 8, 1>(c, a);
     return launch_step_tile<P, 4, 1>(c, a);

@@ -253,6 +253,39 @@ def test_c1_deviation_formats_500_steps(sc, prec):
 
 
 @pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("bc,nxyz,launch", [("ghost", (150, 13, 11), (4, 5, 2)), ("periodic", (150, 13, 11), (4, 2, 2)),
+                                            ("ghost", (70, 9, 7), (4, 100, 2)), ("periodic", (46, 6, 5), (4, 3, 2)),
+                                            ("ghost", (45, 13, 11), (4, 5, 2))])
+def test_two_node_tiles_deviation_formats(sc, prec, bc, nxyz, launch):
+    """The 16-bit formats on a (4, 2) tile with an even nx run one wavefront per
+    128-node row whose lanes own two neighbouring nodes (32-bit population
+    pairs): against the oracle, and bit for bit against 64-node tiles of one
+    node per lane.  nx = 150: a full and a 22-wide tile (values cross between
+    workgroups); nx = 70, 46: one partial tile holding whole rows (periodic
+    wrap inside it); ny, nz ragged against the tile height and z-chunk;
+    nx = 45 (odd) runs the one-node kernel at this shape."""
+    A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
+    steps = 20
+    tab = np.tile(A, (steps, 1))
+    out = []
+    for shape in (launch, (4, 3, 1)):
+        lat, o = make_pair(sc, None, nxyz=nxyz, prec=prec, bc=bc, R=4.0, A=A if bc == "ghost" else None,
+                           steps=steps)
+        lat.set_launch(*shape)
+        if bc == "ghost":
+            lat.set_gradient_table(tab, 0)
+        lat.step(steps)
+        out.append(lat.save())
+        if shape == launch:
+            o.run(steps, tab if bc == "ghost" else None)
+            err = rel_density_error(lat, o)
+            print("%s %s %s: max rel density error %.3e" % (prec, bc, nxyz, err))
+            assert err <= DEV_TOL[prec]
+        lat.close()
+    assert np.array_equal(out[0][64:], out[1][64:])
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
 def test_deviation_formats_stationary_and_checkpoint(sc, prec):
     n = 20
     rho_b = wl.ghost_densities(6.0)
