@@ -204,15 +204,25 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     L fnx[2][Q];
     __half rnx[2] = {__half(0.0f), __half(0.0f)};
     bool nx_in = false;
+    // rows that no other workgroup reads: not a tile edge row in y, not a chunk-end
+    // plane, in a ghost-mode tile holding whole rows (no ring columns taken from it)
+    const bool row_once = GHOST && span && ly > 0 && ly < th - 1;
     auto prefetch = [&](int z) {
         uint32_t vo, nd;
         nx_in = own_node(z, vo, nd);
         if (nx_in) {
+            const bool once = row_once && z > zs && z < ze - 1;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 if (DEV) rnx[s] = ref_in[s * N + nd];
+                if (once) {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) fnx[s][i] = Prec<P>::bload_raw(rs[s], vo, uint32_t(i) * plane_bytes);
+                    for (int i = 0; i < Q; ++i)
+                        fnx[s][i] = Prec<P>::template bload_raw<kLoadNT>(rs[s], vo, uint32_t(i) * plane_bytes);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) fnx[s][i] = Prec<P>::bload_raw(rs[s], vo, uint32_t(i) * plane_bytes);
+                }
             }
         }
     };

@@ -125,16 +125,25 @@ __global__ __launch_bounds__(64 * TY, 2) void k_step_pair(StepArgs a) {
     };
     uint32_t fnx[2][Q], rnx[2] = {0u, 0u};
     bool nx_in = false;
+    // rows that no other workgroup reads (as in k_step): streaming loads
+    const bool row_once = GHOST && span && ly > 0 && ly < th - 1;
     auto prefetch = [&](int z) {
         uint32_t vo, nd;
         nx_in = own_pair(z, vo, nd);
         if (nx_in) {
+            const bool once = row_once && z > zs && z < ze - 1;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 rnx[s] = *reinterpret_cast<const u32a *>(ref_in + s * N + nd);
+                if (once) {
 #pragma unroll
-                for (int i = 0; i < Q; ++i)
-                    fnx[s][i] = __builtin_amdgcn_raw_buffer_load_b32(rs[s], vo, uint32_t(i) * plane_bytes, 0);
+                    for (int i = 0; i < Q; ++i)
+                        fnx[s][i] = __builtin_amdgcn_raw_buffer_load_b32(rs[s], vo, uint32_t(i) * plane_bytes, kLoadNT);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i)
+                        fnx[s][i] = __builtin_amdgcn_raw_buffer_load_b32(rs[s], vo, uint32_t(i) * plane_bytes, 0);
+                }
             }
         }
     };
