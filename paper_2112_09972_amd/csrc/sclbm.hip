@@ -175,9 +175,13 @@ bool uses_pair_kernel(const sclbm_config &c, int ty, int wx) {
     return is_dev(c.prec) && ty == 4 && wx == 2 && c.nx % 2 == 0;
 }
 
-// z-chunk so that the grid holds about two resident waves per SIMD
-// (256 CUs x 4 SIMDs x 2 waves = 2048 waves = 2048 / (TY WX) workgroups).
-// The pair kernel (4 wavefronts, 64 KB of LDS per workgroup; 512 resident) runs
+// z-chunk of a launch.  Two waves per SIMD are resident (the register budget):
+// 256 CUs x 4 SIMDs x 2 = 2048 waves = 2048 / (TY WX) workgroups at a time.  A
+// workgroup's time grows with its planes plus the two it reads beyond its chunk,
+// so the one-node kernel takes the chunk count that minimises (rounds of
+// resident workgroups) x (planes per chunk + 2): a grid slightly larger than the
+// device would otherwise take a second, nearly empty round (measured: 160^3 at
+// 5.4 GLUPS with 320 workgroups).  The pair kernel (4 wavefronts, 64 KB of LDS per workgroup; 512 resident) runs
 // best with about four rounds of resident workgroups and chunks of at least 8
 // planes (measured on 128^3 and 256^3 boxes: 16 chunks in z in both).
 int default_zchunk(const sclbm_config &c, int ty, int wx) {
@@ -186,10 +190,19 @@ int default_zchunk(const sclbm_config &c, int ty, int wx) {
         const long zc = (tiles * c.nz + 2047) / 2048;
         return int(std::max(std::min(8L, long(c.nz)), std::min(zc, long(c.nz))));
     }
-    const long groups = 2048 / (ty * wx);
-    long zc = (tiles * c.nz + groups - 1) / groups;
-    zc = std::max(2L, std::min(zc, long(c.nz)));
-    return int(zc);
+    const long resident = 2048 / (ty * wx);
+    long best_cost = -1, best_zc = c.nz;
+    for (long nzc = 1; nzc <= std::max(1, c.nz / 2); ++nzc) {
+        const long zc = (c.nz + nzc - 1) / nzc;
+        const long chunks = (c.nz + zc - 1) / zc;
+        const long rounds = (tiles * chunks + resident - 1) / resident;
+        const long cost = rounds * (zc + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best_zc = zc;
+        }
+    }
+    return int(best_zc);
 }
 
 // Launch of the step kernel for precision P and a tile of TY rows of WX wavefronts.
