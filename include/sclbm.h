@@ -224,11 +224,14 @@ sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
  * 64-node wavefronts, (tile_rows, tile_waves) one of (4, 1), (8, 1), (4, 2), and
  * planes per z-chunk (>= 1).  A tile as wide as the box's rows lets every
  * x-shifted store write whole cache lines; the default is (4, 2) for nx > 64,
- * else (8, 1).  With the 16-bit deviation formats and an even nx, the (4, 2)
+ * else (8, 1), and (8, 1) also where the last 128-wide tile of a row would be
+ * at most half full (nx mod 128 in 1..64; FP64 and FP32 only).  With the
+ * 16-bit deviation formats and an even nx, the (4, 2)
  * tile runs one wavefront per row whose lanes own two neighbouring nodes each
- * (32-bit accesses of population pairs).  The default z-chunk fills the
- * device about twice over (one-node tiles) or four times over in chunks of
- * at least 8 planes (two-node tiles).  The shape only changes speed, never
+ * (32-bit accesses of population pairs).  The default z-chunk minimises
+ * (rounds of resident workgroups) x (planes per chunk + 2) for one-node
+ * tiles, and fills the device about four times over in chunks of at least
+ * 8 planes for two-node tiles.  The shape only changes speed, never
  * results.  Pointers of get_launch may be NULL. */
 sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk, int32_t tile_waves);
 sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);

@@ -57,6 +57,39 @@ def test_ensemble_equals_independent_boxes(sc, launch):
     assert max(np.max(np.abs(ra - oa) / oa), np.max(np.abs(rb - ob) / ob)) <= 1e-11
 
 
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+def test_deviation_ensemble_two_node_tiles(sc, prec):
+    """16-bit formats on 128 x 4 tiles (two nodes per lane): every box of a
+    3-box ensemble of 70 x 10 x 9 boxes (three z-chunks per box) gives the same
+    fields, bit for bit, as the box run alone on the same tiles and as the box
+    run alone on 64 x 4 tiles of one node per lane."""
+    nxyz, nbox, steps, R = (70, 10, 9), 3, 20, 3.0
+    tabs = [wl.ou_gradient_table(2000 + b, 70, steps, mach=0.1 + 0.05 * b) for b in range(nbox)]
+
+    def lattice(nb, launch):
+        lat = sc.Lattice(*nxyz, nbox=nb, bc="ghost", prec=prec, table_len=steps, g_ab=wl.G_AB,
+                         rho_b=wl.ghost_densities(R))
+        lat.set_launch(*launch)
+        return lat
+
+    ens = lattice(nbox, (4, 3, 2))
+    for b in range(nbox):
+        ens.init_droplet(ens.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0], box=b)
+        ens.set_gradient_table(tabs[b], 0, box=b)
+    ens.step(steps)
+    for b in range(nbox):
+        got = [t.cpu().numpy() for t in ens.fields(box=b)]
+        for launch in ((4, 3, 2), (4, 3, 1)):
+            one = lattice(1, launch)
+            one.init_droplet(one.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0])
+            one.set_gradient_table(tabs[b], 0)
+            one.step(steps)
+            ref = [t.cpu().numpy() for t in one.fields()]
+            assert all(np.array_equal(g, r) for g, r in zip(got, ref)), (b, launch)
+            one.close()
+    ens.close()
+
+
 def test_graph_replays_match_eager(sc):
     """A captured 10-step loop replayed five times, with eager work and
     synchronisations between replays, equals eager stepping after every replay."""
