@@ -159,8 +159,12 @@ sclbm_status check_box(const sclbm_ctx *c, int32_t box, bool allow_all) {
     return SCLBM_OK;
 }
 
-// Tile shapes of the step kernel: (rows, wavefronts per row).
-bool valid_tile(int ty, int wx) { return (ty == 4 && (wx == 1 || wx == 2)) || (ty == 8 && wx == 1); }
+// Tile shapes of the step kernel: (rows, 64-node columns).  (4, 4), 256 nodes
+// wide, exists only for the two-nodes-per-lane kernel of the 16-bit formats.
+bool valid_tile(const sclbm_config &c, int ty, int wx) {
+    if (ty == 4 && wx == 4) return is_dev(c.prec) && c.nx % 2 == 0;
+    return (ty == 4 && (wx == 1 || wx == 2)) || (ty == 8 && wx == 1);
+}
 
 // Default tile: 128 x 4 (whole 128-wide rows: every x-shifted store writes whole
 // cache lines), unless the last 128-wide tile of a row would be at most half
@@ -172,12 +176,18 @@ void default_tile(const sclbm_config &c, int &ty, int &wx) {
     const bool wide = is_dev(c.prec) ? c.nx > 64 : (c.nx > 64 && (tail == 0 || tail > 64));
     wx = wide ? 2 : 1;
     ty = wide ? 4 : 8;
+    // the 16-bit formats: 256-wide tiles of two wavefronts per row where the last
+    // 256-wide tile of a row is full or more than 160 nodes long (FP16, us per
+    // step against 128-wide tiles: 256^3 926 -> 899, 240^3 870 -> 848, 200^3
+    // 615 -> 568, 176^3 461 -> 435; 160^3 406 -> 423 stays on 128-wide tiles)
+    const int tail256 = c.nx % 256;
+    if (valid_tile(c, 4, 4) && c.nx > 128 && (tail256 == 0 || tail256 > 160)) wx = 4;
 }
 
 // Whether a step runs the two-nodes-per-lane kernel (k_step_pair): the 16-bit
-// deviation formats on a 128 x 4 tile with an even nx.
+// deviation formats on a 128 x 4 or 256 x 4 tile with an even nx.
 bool uses_pair_kernel(const sclbm_config &c, int ty, int wx) {
-    return is_dev(c.prec) && ty == 4 && wx == 2 && c.nx % 2 == 0;
+    return is_dev(c.prec) && ty == 4 && (wx == 2 || wx == 4) && c.nx % 2 == 0;
 }
 
 // z-chunk of a launch.  Two waves per SIMD are resident (the register budget):
@@ -188,11 +198,13 @@ bool uses_pair_kernel(const sclbm_config &c, int ty, int wx) {
 // device would otherwise take a second, nearly empty round (measured: 160^3 at
 // 5.4 GLUPS with 320 workgroups).  The pair kernel (4 wavefronts, 64 KB of LDS per workgroup; 512 resident) runs
 // best with about four rounds of resident workgroups and chunks of at least 8
-// planes (measured on 128^3 and 256^3 boxes: 16 chunks in z in both).
+// planes (measured on 128^3 and 256^3 boxes: 16 chunks in z in both; 256-wide
+// tiles hold 128 KB of LDS, one resident workgroup per CU).
 int default_zchunk(const sclbm_config &c, int ty, int wx) {
     const long tiles = long((c.nx + 64 * wx - 1) / (64 * wx)) * long((c.ny + ty - 1) / ty) * c.nbox;
     if (uses_pair_kernel(c, ty, wx)) {
-        const long zc = (tiles * c.nz + 2047) / 2048;
+        const long four_rounds = 4L * (wx == 4 ? 256 : 512);
+        const long zc = (tiles * c.nz + four_rounds - 1) / four_rounds;
         return int(std::max(std::min(8L, long(c.nz)), std::min(zc, long(c.nz))));
     }
     const long resident = 2048 / (ty * wx);
@@ -224,18 +236,25 @@ hipError_t launch_step_tile(sclbm_ctx *c, const StepArgs &a) {
     return hipGetLastError();
 }
 
-// The 16-bit deviation formats on a 128 x 4 tile with an even nx: one wavefront
-// per row, two nodes per lane (same results, half the memory instructions).
+// The 16-bit deviation formats on a 128 x 4 (256 x 4) tile with an even nx: one
+// (two) wavefront(s) per row, two nodes per lane (same results, half the memory
+// instructions).
+template <int P, int WX>
+hipError_t launch_step_pair_w(sclbm_ctx *c, const StepArgs &a) {
+    constexpr int TY = 4;
+    dim3 block(64 * WX, TY, 1);
+    dim3 grid((c->cfg.nx + 128 * WX - 1) / (128 * WX), (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
+    if (c->cfg.bc == SCLBM_BC_GHOST)
+        hipLaunchKernelGGL((k_step_pair<P, TY, WX, true>), grid, block, 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((k_step_pair<P, TY, WX, false>), grid, block, 0, c->stream, a);
+    return hipGetLastError();
+}
+
 template <int P>
 hipError_t launch_step_pair(sclbm_ctx *c, const StepArgs &a) {
-    constexpr int TY = 4;
-    dim3 block(64, TY, 1);
-    dim3 grid((c->cfg.nx + 127) / 128, (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
-    if (c->cfg.bc == SCLBM_BC_GHOST)
-        hipLaunchKernelGGL((k_step_pair<P, TY, true>), grid, block, 0, c->stream, a);
-    else
-        hipLaunchKernelGGL((k_step_pair<P, TY, false>), grid, block, 0, c->stream, a);
-    return hipGetLastError();
+    if (c->tile_waves == 4) return launch_step_pair_w<P, 2>(c, a);
+    return launch_step_pair_w<P, 1>(c, a);
 }
 
 template <int P>
@@ -656,13 +675,14 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
     HIP_TRY(hipEventCreate(&ev1));
     float best = -1.0f;
     int bty = ty_keep, bwx = wx_keep, bzc = zc_keep;
-    const int tys[3] = {4, 8, 4}, wxs[3] = {1, 1, 2};
+    const int tys[4] = {4, 8, 4, 4}, wxs[4] = {1, 1, 2, 4};
     const int zcs[6] = {2, 4, 8, 16, 32, 64};
     sclbm_status result = SCLBM_OK;
-    for (int ti = 0; ti < 3 && result == SCLBM_OK; ++ti)
+    for (int ti = 0; ti < 4 && result == SCLBM_OK; ++ti)
         for (int zi = 0; zi < 6 && result == SCLBM_OK; ++zi) {
             if (zcs[zi] > c->cfg.nz && zi > 0 && zcs[zi - 1] >= c->cfg.nz) continue;
-            if (wxs[ti] > 1 && c->cfg.nx <= 64) continue;  // a second wavefront would hold no nodes
+            if (!valid_tile(c->cfg, tys[ti], wxs[ti])) continue;
+            if (c->cfg.nx <= 64 * (wxs[ti] / 2)) continue;  // the tile's last column would hold no nodes
             c->tile_rows = tys[ti];
             c->tile_waves = wxs[ti];
             c->zchunk = std::min(zcs[zi], c->cfg.nz);
@@ -982,8 +1002,10 @@ sclbm_status sclbm_load(sclbm_ctx *c, const void *host_buf, size_t bytes) {
 sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk, int32_t tile_waves) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
-    if (!valid_tile(tile_rows, tile_waves))
-        return fail(SCLBM_EINVAL, "tile (rows %d, waves %d) must be (4, 1), (8, 1) or (4, 2)", tile_rows, tile_waves);
+    if (!valid_tile(c->cfg, tile_rows, tile_waves))
+        return fail(SCLBM_EINVAL,
+                    "tile (rows %d, waves %d) must be (4, 1), (8, 1), (4, 2), or (4, 4) with a 16-bit format and even nx",
+                    tile_rows, tile_waves);
     if (zchunk < 1) return fail(SCLBM_EINVAL, "zchunk must be >= 1");
     c->tile_rows = tile_rows;
     c->tile_waves = tile_waves;

@@ -26,14 +26,14 @@
 
 namespace sclbm {
 
-template <int P, int TY, bool GHOST>
-__global__ __launch_bounds__(64 * TY, 2) void k_step_pair(StepArgs a) {
+template <int P, int TY, int WX, bool GHOST>
+__global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
     static_assert(Prec<P>::DEV, "two nodes per lane: the 16-bit deviation formats");
     using R = typename Prec<P>::R;  // float
     using W = typename Prec<P>::W;  // float
     using C = R;
     using L = typename Prec<P>::L;  // unsigned short
-    constexpr int TXW = 128;        // nodes per tile row: 64 lanes x 2
+    constexpr int TXW = 128 * WX;   // nodes per tile row: WX wavefronts of 64 lanes x 2
     constexpr int LW = TXW + 2;
     constexpr uint32_t EB = 2;
     typedef uint32_t __attribute__((may_alias)) u32a;
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64 * TY, 2) void k_step_pair(StepArgs a) {
     auto col0 = [](int i) { return cx_of(i) != 0 ? 1 : 0; };
 
     const int lx = threadIdx.x, ly = threadIdx.y;
-    const int tid = ly * 64 + lx;
+    const int tid = ly * 64 * WX + lx;
     // tile order: as in k_step (contiguous runs per XCD, z-chunks grouped)
     const uint32_t nbx = gridDim.x, nby = gridDim.y;
     const uint32_t nb = nbx * nby * gridDim.z;
@@ -172,10 +172,11 @@ __global__ __launch_bounds__(64 * TY, 2) void k_step_pair(StepArgs a) {
                 lds[slot][1][ly + 1][1 + n0 + j] = own_in ? pair_node_density(fcur[1], rcur[1], j) : rhob[1];
             }
         }
-        // ring rows y0 - 1 and y0 + th as pairs (threads 0-127), the two ring
-        // columns node by node (threads 128 ...)
-        if (tid < 128) {
-            const int p = tid & 63, side = tid >> 6;
+        // ring rows y0 - 1 and y0 + th as pairs (threads 0 .. TXW - 1), the two ring
+        // columns node by node (threads TXW ...)
+        static_assert(TXW + 2 * (TY + 2) <= 64 * WX * TY, "one ring pair or node per thread");
+        if (tid < TXW) {
+            const int p = tid % (TXW / 2), side = tid / (TXW / 2);
             const int rsy = side ? th + 1 : 0;
             if (2 * p < tw) {
                 int gy = y0 - 1 + rsy, gz = z;
@@ -207,8 +208,8 @@ __global__ __launch_bounds__(64 * TY, 2) void k_step_pair(StepArgs a) {
                     lds[slot][1][rsy][1 + 2 * p + j] = rr[j][1];
                 }
             }
-        } else if (tid < 128 + 2 * (th + 2)) {
-            const int r = tid - 128, side = r / (th + 2), rsy = r % (th + 2);
+        } else if (tid < TXW + 2 * (th + 2)) {
+            const int r = tid - TXW, side = r / (th + 2), rsy = r % (th + 2);
             const int rsx = side ? tw + 1 : 0;
             int gx = x0 - 1 + rsx, gy = y0 - 1 + rsy, gz = z;
             bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;

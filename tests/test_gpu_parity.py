@@ -196,8 +196,9 @@ def test_step_past_table_and_mach_errors(sc):
     with pytest.raises(sc.SclbmError) as ei:
         lat.set_gradient_table(np.tile(wl.simple_shear(0.05), (10, 1)), 10)
     assert ei.value.status == sc.SCLBM_EINVAL and "ghost speed" in str(ei.value)
-    # tile shapes outside (4, 1), (8, 1), (4, 2) and z-chunks below 1 are refused
-    for bad in [(2, 16, 2), (8, 16, 2), (4, 16, 3), (6, 16, 1), (4, 0, 1)]:
+    # tile shapes outside (4, 1), (8, 1), (4, 2) and z-chunks below 1 are refused;
+    # (4, 4) exists only for the 16-bit formats
+    for bad in [(2, 16, 2), (8, 16, 2), (4, 16, 3), (6, 16, 1), (4, 0, 1), (4, 16, 4)]:
         with pytest.raises(sc.SclbmError) as ei:
             lat.set_launch(*bad)
         assert ei.value.status == sc.SCLBM_EINVAL
@@ -255,15 +256,19 @@ def test_c1_deviation_formats_500_steps(sc, prec):
 @pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
 @pytest.mark.parametrize("bc,nxyz,launch", [("ghost", (150, 13, 11), (4, 5, 2)), ("periodic", (150, 13, 11), (4, 2, 2)),
                                             ("ghost", (70, 9, 7), (4, 100, 2)), ("periodic", (46, 6, 5), (4, 3, 2)),
-                                            ("ghost", (45, 13, 11), (4, 5, 2))])
+                                            ("ghost", (45, 13, 11), (4, 5, 2)), ("ghost", (150, 13, 11), (4, 5, 4)),
+                                            ("periodic", (150, 13, 11), (4, 2, 4)), ("ghost", (300, 6, 5), (4, 2, 4)),
+                                            ("periodic", (270, 6, 5), (4, 3, 4))])
 def test_two_node_tiles_deviation_formats(sc, prec, bc, nxyz, launch):
-    """The 16-bit formats on a (4, 2) tile with an even nx run one wavefront per
-    128-node row whose lanes own two neighbouring nodes (32-bit population
-    pairs): against the oracle, and bit for bit against 64-node tiles of one
-    node per lane.  nx = 150: a full and a 22-wide tile (values cross between
-    workgroups); nx = 70, 46: one partial tile holding whole rows (periodic
-    wrap inside it); ny, nz ragged against the tile height and z-chunk;
-    nx = 45 (odd) runs the one-node kernel at this shape."""
+    """The 16-bit formats on a (4, 2) or (4, 4) tile with an even nx run one or
+    two wavefronts per 128- or 256-node row whose lanes own two neighbouring
+    nodes (32-bit population pairs): against the oracle, and bit for bit
+    against 64-node tiles of one node per lane.  nx = 150 on (4, 2): a full and
+    a 22-wide tile (values cross between workgroups); nx = 150 on (4, 4), 70,
+    46: one partial tile holding whole rows (periodic wrap inside it); nx = 300,
+    270 on (4, 4): a full 256-wide tile and a 44- or 14-wide one; ny, nz ragged
+    against the tile height and z-chunk; nx = 45 (odd) runs the one-node
+    kernel at (4, 2)."""
     A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
     steps = 20
     tab = np.tile(A, (steps, 1))
@@ -272,6 +277,10 @@ def test_two_node_tiles_deviation_formats(sc, prec, bc, nxyz, launch):
         lat, o = make_pair(sc, None, nxyz=nxyz, prec=prec, bc=bc, R=4.0, A=A if bc == "ghost" else None,
                            steps=steps)
         lat.set_launch(*shape)
+        if nxyz[0] % 2:
+            with pytest.raises(sc.SclbmError) as ei:
+                lat.set_launch(4, 5, 4)  # two nodes per lane need an even nx
+            assert ei.value.status == sc.SCLBM_EINVAL
         if bc == "ghost":
             lat.set_gradient_table(tab, 0)
         lat.step(steps)
