@@ -11,15 +11,15 @@
 // a run is a 32-bit pair: a wavefront covers 128 nodes of a row and each of its
 // loads and stores moves 256 bytes.
 //
-// Layout and tiling as in k_step with a 128 x TY tile (row-blocked populations,
-// march along a z-chunk, 4-slot LDS density window, raw next-plane prefetch,
-// alternating march directions, grouped z-chunks in the tile order), but one
-// wavefront per row.  The register window holds raw pairs, decoded node by node
-// when the densities are summed and again when the plane collides.  Every
-// post-collision value goes to LDS; after the second barrier each lane reads,
-// per direction, the pair pushed into its two nodes as one aligned 32-bit LDS
-// word and stores it as one 32-bit word.  Requires an even nx (pairs 4-byte
-// aligned, the tile's width even).
+// Layout and tiling as in k_step with a 128 WX x TY tile (row-blocked
+// populations, march along a z-chunk, 4-slot LDS density window, raw next-plane
+// prefetch, streaming loads of rows read once, alternating march directions,
+// grouped z-chunks in the tile order), with WX wavefronts per row.  The
+// register window holds raw pairs, decoded node by node when the densities are
+// summed and again when the plane collides.  Every post-collision value goes to
+// LDS; after the second barrier each lane reads, per direction, the pair pushed
+// into its two nodes as one aligned 32-bit LDS word and stores it as one 32-bit
+// word.  Requires an even nx (pairs 4-byte aligned, the tile's width even).
 #pragma once
 
 #include "step_kernel.hpp"
