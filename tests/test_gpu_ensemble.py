@@ -90,15 +90,19 @@ def test_deviation_ensemble_two_node_tiles(sc, prec):
     ens.close()
 
 
-def test_graph_replays_match_eager(sc):
+@pytest.mark.parametrize("prec,nx,launch", [("f32", 20, None), ("f16dev", 150, (4, 3, 4)), ("bf16dev", 100, (4, 3, 2))])
+def test_graph_replays_match_eager(sc, prec, nx, launch):
     """A captured 10-step loop replayed five times, with eager work and
-    synchronisations between replays, equals eager stepping after every replay."""
+    synchronisations between replays, equals eager stepping after every replay
+    (also for the two-nodes-per-lane kernel of the 16-bit formats)."""
     n, nbox, steps, R = 20, 2, 60, 4.0
-    tabs = ou_tables(n, nbox, steps, seed0=77)
+    tabs = ou_tables(nx, nbox, steps, seed0=77)
 
     def make():
-        lat = sc.Lattice(n, n, n, nbox=nbox, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB,
+        lat = sc.Lattice(nx, n, n, nbox=nbox, bc="ghost", prec=prec, table_len=steps, g_ab=wl.G_AB,
                          rho_b=wl.ghost_densities(R))
+        if launch:
+            lat.set_launch(*launch)
         for b in range(nbox):
             lat.init_droplet(lat.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0], box=b)
             lat.set_gradient_table(tabs[b], 0, box=b)
