@@ -204,6 +204,9 @@ def main():
     ap.add_argument("--surrogate-train-steps", type=int, default=10000)
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
+    ap.add_argument("--format-steps", type=int, default=0,
+                    help="only run this many steps of the 128^3 box in FP32 and in FP64 storage, default launch "
+                         "(for per-kernel counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs the hot path on a single MI355X "
@@ -225,6 +228,19 @@ def main():
     from paper_2112_09972_amd import workloads as wl
     if args.workload == "c3":
         precision_study(sc, args.c3_steps)
+        return
+    if args.format_steps > 0:
+        case = wl.case_c2(nsteps=args.format_steps + 1)
+        tab = case.tables[0]
+        for prec in ("f32", "f64"):
+            lat = sc.Lattice(case.n, case.n, case.n, bc="ghost", prec=prec, table_len=args.format_steps,
+                             g_ab=wl.G_AB, rho_b=case.rho_b, mach_max=wl.MACH_MAX)
+            lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
+            lat.set_gradient_table(tab[:args.format_steps], 0)
+            lat.step(args.format_steps)
+            lat.synchronize()
+            print(json.dumps({"format": prec, "steps": args.format_steps, "launch": lat.get_launch()}), flush=True)
+            lat.close()
         return
 
     K, W = args.steps, args.warmup
