@@ -239,6 +239,11 @@ sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
 sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk, int32_t tile_waves);
 sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);
 
+/* The launch shape a context with this configuration starts with (the
+ * defaults above), computed on the host without a device.  Pointers may be
+ * NULL.  Errors: EINVAL for an invalid configuration. */
+sclbm_status sclbm_default_launch(const sclbm_config *cfg, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);
+
 /* Autotuner: time trial_steps steps (after one warm-up step) for every tile
  * shape ((4, 1), (8, 1), (4, 2) when nx > 64, and (4, 4) where it is valid
  * and nx > 128) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz), keep the

@@ -51,7 +51,7 @@ EXPORTS = [
     "sclbm_workspace_bytes", "sclbm_create", "sclbm_destroy", "sclbm_init_droplet", "sclbm_init_fields",
     "sclbm_set_gradient_table", "sclbm_step", "sclbm_get_step", "sclbm_fields", "sclbm_totals",
     "sclbm_droplet_moments", "sclbm_droplet_from_moments", "sclbm_droplet", "sclbm_velocity_error",
-    "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch",
+    "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch", "sclbm_default_launch",
     "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune", "sclbm_droplet_moments_all", "sclbm_mm_integrate",
     "sclbm_droplet_surface_all", "sclbm_deformation_lbm", "sclbm_droplet_mass_all", "sclbm_reinject",
     # droplet-shape surrogate (sclmlp.h)
@@ -103,6 +103,7 @@ def _load_library():
         "sclbm_load": [P, P, ctypes.c_size_t],
         "sclbm_set_launch": [P, I32, I32, I32],
         "sclbm_get_launch": [P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)],
+        "sclbm_default_launch": [cfgp, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)],
         "sclmlp_workspace_bytes": [I64, ctypes.POINTER(ctypes.c_size_t)],
         "sclmlp_create": [I64, P, ctypes.c_size_t, P, ctypes.POINTER(P)],
         "sclmlp_destroy": [P],
@@ -301,6 +302,16 @@ def sclbm_get_launch(ctx):
     z = ctypes.c_int32()
     w = ctypes.c_int32()
     _check(_lib.sclbm_get_launch(ctx, ctypes.byref(t), ctypes.byref(z), ctypes.byref(w)))
+    return t.value, z.value, w.value
+
+
+def sclbm_default_launch(cfg: sclbm_config):
+    """The launch shape a context with this configuration starts with,
+    computed on the host: (tile_rows, zchunk, tile_waves)."""
+    t = ctypes.c_int32()
+    z = ctypes.c_int32()
+    w = ctypes.c_int32()
+    _check(_lib.sclbm_default_launch(ctypes.byref(cfg), ctypes.byref(t), ctypes.byref(z), ctypes.byref(w)))
     return t.value, z.value, w.value
 
 

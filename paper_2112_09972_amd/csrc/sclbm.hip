@@ -441,6 +441,17 @@ sclbm_status sclbm_workspace_bytes(const sclbm_config *cfg, size_t *bytes) {
     return SCLBM_OK;
 }
 
+sclbm_status sclbm_default_launch(const sclbm_config *cfg, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves) {
+    std::string why;
+    if (!config_ok(cfg, why)) return fail(SCLBM_EINVAL, "invalid config: %s", why.c_str());
+    int ty = 0, wx = 0;
+    default_tile(*cfg, ty, wx);
+    if (tile_rows) *tile_rows = ty;
+    if (zchunk) *zchunk = default_zchunk(*cfg, ty, wx);
+    if (tile_waves) *tile_waves = wx;
+    return SCLBM_OK;
+}
+
 sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
                           sclbm_ctx **out) {
     std::string why;

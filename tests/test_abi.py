@@ -108,3 +108,34 @@ def test_empty_droplet():
     got = sc.sclbm_droplet_from_moments(np.zeros(10), [1.0, 2.0, 3.0])
     assert got["volume"] == 0.0 and np.all(got["semi_axes"] == 0.0)
     assert np.allclose(got["com"], [1, 2, 3])
+
+
+@pytest.mark.parametrize("n,nbox,prec,expect", [
+    (128, 1, 1, (4, 16, 2)),   # benchmark box: whole 128-wide rows, 256 workgroups in one round
+    (256, 1, 1, (4, 128, 2)),  # two tiles per row, two chunks: one round
+    (64, 64, 1, (8, 64, 1)),   # ensemble of 64^3 boxes: whole-box chunks, two rounds
+    (160, 1, 1, (8, 40, 1)),   # last 128-wide tile a quarter full: 64 x 8 tiles
+    (192, 1, 1, (8, 28, 1)),   # last 128-wide tile half full: 64 x 8 tiles; two rounds of 30
+    (96, 1, 1, (4, 10, 2)),    # 240 workgroups, not 264 (a second, nearly empty round)
+    (200, 1, 1, (4, 40, 2)),
+    (32, 1, 0, (8, 2, 1)),
+    (256, 1, 2, (4, 16, 4)),   # 16-bit formats: 256-wide pair tiles, four rounds of 256
+    (200, 1, 3, (4, 10, 4)),
+    (160, 1, 2, (4, 8, 2)),    # last 256-wide tile 160 nodes: 128-wide pair tiles, at least 8 planes
+    (150, 1, 2, (4, 8, 2)),
+    (45, 1, 2, (8, 3, 1)),     # odd nx: one node per lane
+])
+def test_default_launch_rules(n, nbox, prec, expect):
+    """The default launch shape (tile rows, z-chunk, 64-node columns) a context
+    starts with, computed on the host: the tile and z-chunk rules for one-node
+    tiles (fill of the last tile, rounds of resident workgroups times planes per
+    chunk) and for the two-nodes-per-lane tiles of the 16-bit formats."""
+    import paper_2112_09972_amd as sc
+    assert sc.sclbm_default_launch(cfg(nx=n, ny=n, nz=n, nbox=nbox, prec=prec)) == expect
+
+
+def test_default_launch_rejects_invalid_config():
+    import paper_2112_09972_amd as sc
+    with pytest.raises(sc.SclbmError) as ei:
+        sc.sclbm_default_launch(cfg(nx=2))
+    assert ei.value.status == sc.SCLBM_EINVAL

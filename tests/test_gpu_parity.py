@@ -205,6 +205,15 @@ def test_step_past_table_and_mach_errors(sc):
     assert lat.get_launch()[0] in (4, 8)
 
 
+@pytest.mark.parametrize("nxyz,prec", [((40, 12, 9), "f32"), ((150, 6, 5), "f16dev"), ((180, 4, 4), "bf16dev"),
+                                       ((160, 8, 8), "f64")])
+def test_context_starts_at_default_launch(sc, nxyz, prec):
+    """A context starts at the launch shape sclbm_default_launch computes on the host."""
+    lat = sc.Lattice(*nxyz, bc="ghost", prec=prec, g_ab=wl.G_AB, rho_b=wl.ghost_densities(3.0))
+    assert lat.get_launch() == sc.sclbm_default_launch(lat.cfg)
+    lat.close()
+
+
 def test_full_size_128_fp32_all_nodes(sc):
     """The 128^3 FP32 box at the benchmark's launch shape against the oracle on
     every node after 6 steps of the OU drive."""
