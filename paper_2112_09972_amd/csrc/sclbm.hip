@@ -169,8 +169,8 @@ bool valid_tile(const sclbm_config &c, int ty, int wx) {
 // Default tile: 128 x 4 (whole 128-wide rows: every x-shifted store writes whole
 // cache lines), unless the last 128-wide tile of a row would be at most half
 // full; then 64 x 8, which leaves fewer idle lanes (measured at 160^3: 402
-// against 463 us per step).  The 16-bit formats keep 128 x 4 for any nx > 64:
-// that tile runs their two-nodes-per-lane kernel.
+// against 463 us per step).  The 16-bit formats take 128 x 4 for any nx > 64,
+// the tile of their two-nodes-per-lane kernel, or 256 x 4 (below).
 void default_tile(const sclbm_config &c, int &ty, int &wx) {
     const int tail = c.nx % 128;
     const bool wide = is_dev(c.prec) ? c.nx > 64 : (c.nx > 64 && (tail == 0 || tail > 64));
@@ -196,10 +196,11 @@ bool uses_pair_kernel(const sclbm_config &c, int ty, int wx) {
 // so the one-node kernel takes the chunk count that minimises (rounds of
 // resident workgroups) x (planes per chunk + 2): a grid slightly larger than the
 // device would otherwise take a second, nearly empty round (measured: 160^3 at
-// 5.4 GLUPS with 320 workgroups).  The pair kernel (4 wavefronts, 64 KB of LDS per workgroup; 512 resident) runs
-// best with about four rounds of resident workgroups and chunks of at least 8
-// planes (measured on 128^3 and 256^3 boxes: 16 chunks in z in both; 256-wide
-// tiles hold 128 KB of LDS, one resident workgroup per CU).
+// 5.4 GLUPS with 320 workgroups).  The pair kernel runs best with about four
+// rounds of resident workgroups and chunks of at least 8 planes (measured on
+// 128^3 and 256^3 boxes: 16 chunks in z in both); its 128-wide tiles (4
+// wavefronts, 64 KB of LDS) have 512 resident workgroups, its 256-wide tiles
+// (8 wavefronts, 128 KB) 256.
 int default_zchunk(const sclbm_config &c, int ty, int wx) {
     const long tiles = long((c.nx + 64 * wx - 1) / (64 * wx)) * long((c.ny + ty - 1) / ty) * c.nbox;
     if (uses_pair_kernel(c, ty, wx)) {
