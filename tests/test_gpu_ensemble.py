@@ -57,9 +57,9 @@ def test_ensemble_equals_independent_boxes(sc, launch):
     assert max(np.max(np.abs(ra - oa) / oa), np.max(np.abs(rb - ob) / ob)) <= 1e-11
 
 
-@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
-def test_deviation_ensemble_two_node_tiles(sc, prec):
-    """16-bit formats on 128 x 4 tiles (two nodes per lane): every box of a
+@pytest.mark.parametrize("prec,wide", [("f16dev", 2), ("bf16dev", 2), ("f16dev", 4)])
+def test_deviation_ensemble_two_node_tiles(sc, prec, wide):
+    """16-bit formats on 128 x 4 or 256 x 4 tiles (two nodes per lane): every box of a
     3-box ensemble of 70 x 10 x 9 boxes (three z-chunks per box) gives the same
     fields, bit for bit, as the box run alone on the same tiles and as the box
     run alone on 64 x 4 tiles of one node per lane."""
@@ -72,14 +72,14 @@ def test_deviation_ensemble_two_node_tiles(sc, prec):
         lat.set_launch(*launch)
         return lat
 
-    ens = lattice(nbox, (4, 3, 2))
+    ens = lattice(nbox, (4, 3, wide))
     for b in range(nbox):
         ens.init_droplet(ens.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0], box=b)
         ens.set_gradient_table(tabs[b], 0, box=b)
     ens.step(steps)
     for b in range(nbox):
         got = [t.cpu().numpy() for t in ens.fields(box=b)]
-        for launch in ((4, 3, 2), (4, 3, 1)):
+        for launch in ((4, 3, wide), (4, 3, 1)):
             one = lattice(1, launch)
             one.init_droplet(one.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tabs[b][0])
             one.set_gradient_table(tabs[b], 0)
@@ -125,18 +125,24 @@ def test_graph_replays_match_eager(sc, prec, nx, launch):
     assert np.array_equal(g.save(), e.save())
 
 
-def test_autotune_keeps_results(sc):
-    n, steps, R = 40, 30, 8.0
-    A = wl.simple_shear(0.002)
-    lat = sc.Lattice(n, n, n, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
+@pytest.mark.parametrize("prec,nxyz,shapes", [
+    ("f32", (40, 40, 40), ((4, 1), (8, 1))),                        # nx <= 64: one column of 64 nodes
+    ("f16dev", (150, 12, 10), ((4, 1), (8, 1), (4, 2), (4, 4))),   # 16-bit, nx > 128: pair tiles too
+])
+def test_autotune_keeps_results(sc, prec, nxyz, shapes):
+    """The autotuner sets a valid shape of those it may try, restores the time, and
+    the tuned context gives the same bits as one at the default launch."""
+    n, steps, R = nxyz[0], 30, 5.0
+    A = wl.simple_shear(0.0006)
+    lat = sc.Lattice(*nxyz, bc="ghost", prec=prec, table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
     lat.set_gradient_table(np.tile(A, (steps, 1)), 0)
     ty, zc, wx, ms = sc.sclbm_autotune(lat.ctx, 3)
-    assert (ty, wx) in ((4, 1), (8, 1)) and 1 <= zc <= n and ms > 0   # nx <= 64: one wavefront per row
+    assert (ty, wx) in shapes and 1 <= zc <= nxyz[2] and ms > 0
     assert lat.get_launch() == (ty, zc, wx)
     assert lat.step_count == 0
     lat.init_droplet(lat.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
     lat.step(steps)
-    ref = sc.Lattice(n, n, n, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
+    ref = sc.Lattice(*nxyz, bc="ghost", prec=prec, table_len=steps, g_ab=wl.G_AB, rho_b=wl.ghost_densities(R))
     ref.set_gradient_table(np.tile(A, (steps, 1)), 0)
     ref.init_droplet(ref.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
     ref.step(steps)
