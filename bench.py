@@ -296,11 +296,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": case.name, "box": case.n, "radius": case.radius, "lattice_steps_per_step": STRIDE,
                    "lattice_steps_timed": STRIDE * K, "tau": case.tau, "g_ab": wl.G_AB,
-                   "storage": "fp32 row-blocked SoA, 2x19 populations (arithmetic fp64)", "launch": {"tile_rows": ty, "zchunk": zc, "tile_waves": wx},
+                   "storage": "fp32 row-blocked SoA, 2x19 populations", "arithmetic": "fp32 (fp64 totals and moments)", "launch": {"tile_rows": ty, "zchunk": zc, "tile_waves": wx},
                    "ca_max": round(float(ca.max()), 4), "ca_mean": round(float(ca.mean()), 4),
                    "mass_drift_rel": [float(v) for v in ((m1 - m0) / m0)],
                    "semi_axes_last": [round(float(v), 4) for v in axes[-1]]},

@@ -62,7 +62,7 @@ typedef enum {
 
 typedef enum {
     SCLBM_F64 = 0,    /* FP64 populations, FP64 arithmetic */
-    SCLBM_F32 = 1,    /* FP32 populations, FP64 arithmetic */
+    SCLBM_F32 = 1,    /* FP32 populations, FP32 arithmetic */
     SCLBM_F16DEV = 2, /* FP16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
     SCLBM_BF16DEV = 3 /* BF16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
 } sclbm_prec;
@@ -246,8 +246,9 @@ sclbm_status sclbm_default_launch(const sclbm_config *cfg, int32_t *tile_rows, i
 
 /* Autotuner: time trial_steps steps (after one warm-up step) for every tile
  * shape ((4, 1), (8, 1), (4, 2) when nx > 64, and (4, 4) where it is valid
- * and nx > 128) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz), keep the
- * fastest and set it.  The output pointers
+ * and nx > 128) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz, and the
+ * tile's default z-chunk, so the default launch is one of the candidates),
+ * keep the fastest and set it.  The output pointers
  * (may be NULL) receive its shape and the best average step time in ms.
  * The trials overwrite the populations (call it before an init call, or
  * re-initialise after) but restore the time.  In ghost mode every box's table

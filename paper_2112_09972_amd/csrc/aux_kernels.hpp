@@ -102,22 +102,23 @@ __device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, const
     using R = typename Prec<P>::R;
     const int64_t N = g.nnode;
     const int64_t e = pop_base(g, k);
+    // the populations as stored (decoded in the format's arithmetic type), summed in FP64
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        R r = R(0), jx = R(0), jy = R(0), jz = R(0);
+        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
         const R rref = Prec<P>::DEV ? R(ref_load(ref + s * N + k)) : R(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R v = R(Prec<P>::load(f + (int64_t)s * Q * N + e + (int64_t)i * g.nx, w_of<R>(i) * rref));
+            const double v = double(Prec<P>::load(f + (int64_t)s * Q * N + e + (int64_t)i * g.nx, w_of<R>(i) * rref));
             r += v;
-            if (cx_of(i)) jx += R(cx_of(i)) * v;
-            if (cy_of(i)) jy += R(cy_of(i)) * v;
-            if (cz_of(i)) jz += R(cz_of(i)) * v;
+            if (cx_of(i)) jx += double(cx_of(i)) * v;
+            if (cy_of(i)) jy += double(cy_of(i)) * v;
+            if (cz_of(i)) jz += double(cz_of(i)) * v;
         }
-        rho[s] = double(r);
-        j[s][0] = double(jx);
-        j[s][1] = double(jy);
-        j[s][2] = double(jz);
+        rho[s] = r;
+        j[s][0] = jx;
+        j[s][1] = jy;
+        j[s][2] = jz;
     }
 }
 

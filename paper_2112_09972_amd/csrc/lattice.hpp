@@ -52,11 +52,13 @@ __host__ __device__ constexpr R w_of(int i) {
 
 // Storage formats.  S is what lives in HBM, W the type a loaded population is
 // held in registers (exactly representable from S), R the arithmetic type.
-// FP32 storage computes in FP64: on gfx950 the FP64 vector rate equals the
-// unpacked FP32 rate, and FP32 collide arithmetic drifts (the FP32-rounded
-// lattice weights do not sum to one, so every collision creates or destroys a
-// little mass; after 500 steps of the droplet box the densities are off by
-// 2e-5, about 100x the storage rounding).
+// FP32 storage computes in FP32.  The FP32-rounded lattice weights do not sum
+// to one (1 + 3e-8), so a single-rate collision written population by
+// population would create or destroy that much mass at every node and step
+// (2e-5 density error after 500 steps of the droplet box); the step kernel
+// therefore lets the rest population close the mass balance, rho minus the
+// other eighteen post-collision values, which is the same update in exact
+// arithmetic.
 // The deviation formats hold d_i = f_i / (w_i rho_ref(x)) - 1 in 16 bits with FP32
 // arithmetic, rho_ref(x) being the node's own density one step earlier, kept
 // per node and component in FP16 (DEV = true).  A constant reference fails in
@@ -97,6 +99,7 @@ struct Prec<SCLBM_F64> {
     using S = double;
     using W = double;
     using R = double;
+    using D = double;  // densities of the force stencil
     static __device__ __forceinline__ W load(const S *p, R /*wref*/) { return *p; }
     static __device__ __forceinline__ void store(S *p, R v, R /*wref*/) { *p = v; }
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R /*wref*/) {
@@ -122,7 +125,8 @@ struct Prec<SCLBM_F32> {
     static constexpr bool DEV = false;
     using S = float;
     using W = float;
-    using R = double;
+    using R = float;
+    using D = double;
     static __device__ __forceinline__ W load(const S *p, R /*wref*/) { return *p; }
     static __device__ __forceinline__ void store(S *p, R v, R /*wref*/) { *p = float(v); }
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R /*wref*/) {
@@ -149,6 +153,7 @@ struct Prec<SCLBM_F16DEV> {
     using S = __half;
     using W = float;
     using R = float;
+    using D = float;
     static __device__ __forceinline__ W load(const S *p, R wref) { return wref + wref * __half2float(*p); }
     static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2half_rn(rel_dev(v, wref)); }
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {
@@ -180,6 +185,7 @@ struct Prec<SCLBM_BF16DEV> {
     using S = __hip_bfloat16;
     using W = float;
     using R = float;
+    using D = float;
     static __device__ __forceinline__ W load(const S *p, R wref) { return wref + wref * __bfloat162float(*p); }
     static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2bfloat16(rel_dev(v, wref)); }
     static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {

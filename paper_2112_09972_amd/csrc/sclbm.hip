@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -687,39 +688,48 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
     HIP_TRY(hipEventCreate(&ev1));
     float best = -1.0f;
     int bty = ty_keep, bwx = wx_keep, bzc = zc_keep;
+    // candidates: every valid tile with z-chunks 2 .. 64 (capped at nz) and the
+    // tile's default z-chunk, so that the default launch is always among them
     const int tys[4] = {4, 8, 4, 4}, wxs[4] = {1, 1, 2, 4};
     const int zcs[6] = {2, 4, 8, 16, 32, 64};
+    std::vector<std::array<int, 3>> cand;
+    for (int ti = 0; ti < 4; ++ti) {
+        if (!valid_tile(c->cfg, tys[ti], wxs[ti])) continue;
+        if (c->cfg.nx <= 64 * (wxs[ti] / 2)) continue;  // the tile's last column would hold no nodes
+        std::vector<int> zl;
+        for (int zc : zcs) zl.push_back(std::min(zc, c->cfg.nz));
+        zl.push_back(default_zchunk(c->cfg, tys[ti], wxs[ti]));
+        std::sort(zl.begin(), zl.end());
+        zl.erase(std::unique(zl.begin(), zl.end()), zl.end());
+        for (int zc : zl) cand.push_back({tys[ti], wxs[ti], zc});
+    }
     sclbm_status result = SCLBM_OK;
-    for (int ti = 0; ti < 4 && result == SCLBM_OK; ++ti)
-        for (int zi = 0; zi < 6 && result == SCLBM_OK; ++zi) {
-            if (zcs[zi] > c->cfg.nz && zi > 0 && zcs[zi - 1] >= c->cfg.nz) continue;
-            if (!valid_tile(c->cfg, tys[ti], wxs[ti])) continue;
-            if (c->cfg.nx <= 64 * (wxs[ti] / 2)) continue;  // the tile's last column would hold no nodes
-            c->tile_rows = tys[ti];
-            c->tile_waves = wxs[ti];
-            c->zchunk = std::min(zcs[zi], c->cfg.nz);
-            int64_t clk[2] = {n0, n0};
-            hipError_t e = hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = enqueue_steps(c, 1, par0 ^ 0);  // warm-up (reads row n0)
-            if (e == hipSuccess) e = hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(ev0, c->stream);
-            if (e == hipSuccess) e = enqueue_steps(c, trial_steps, par0);
-            if (e == hipSuccess) e = hipEventRecord(ev1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(ev1);
-            float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-            if (e != hipSuccess) {
-                result = fail(SCLBM_EHIP, "autotune: %s", hipGetErrorString(e));
-                break;
-            }
-            ms /= float(trial_steps);
-            if (best < 0.0f || ms < best) {
-                best = ms;
-                bty = c->tile_rows;
-                bwx = c->tile_waves;
-                bzc = c->zchunk;
-            }
+    for (size_t ci = 0; ci < cand.size() && result == SCLBM_OK; ++ci) {
+        c->tile_rows = cand[ci][0];
+        c->tile_waves = cand[ci][1];
+        c->zchunk = cand[ci][2];
+        int64_t clk[2] = {n0, n0};
+        hipError_t e = hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = enqueue_steps(c, 1, par0 ^ 0);  // warm-up (reads row n0)
+        if (e == hipSuccess) e = hipMemcpyAsync(c->clock(), clk, sizeof clk, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev0, c->stream);
+        if (e == hipSuccess) e = enqueue_steps(c, trial_steps, par0);
+        if (e == hipSuccess) e = hipEventRecord(ev1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+        if (e != hipSuccess) {
+            result = fail(SCLBM_EHIP, "autotune: %s", hipGetErrorString(e));
+            break;
         }
+        ms /= float(trial_steps);
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            bty = c->tile_rows;
+            bwx = c->tile_waves;
+            bzc = c->zchunk;
+        }
+    }
     (void)hipEventDestroy(ev0);  // teardown: nothing to do on failure
     (void)hipEventDestroy(ev1);
     // restore the time; the populations hold trial results

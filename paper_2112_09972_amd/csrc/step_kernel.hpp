@@ -35,6 +35,15 @@
 // the same access pattern without arithmetic runs at 3.7 TB/s with shifted
 // stores and 5.1 TB/s with whole-line ones.)  Stores are non-temporal.
 //
+// Precision.  FP64 storage computes in FP64.  FP32 and the 16-bit formats
+// compute the collision in FP32; with FP32 storage the densities of the force
+// stencil are summed in FP64 (from the FP32 populations, so exactly up to the
+// storage rounding): the stencil takes differences of neighbouring densities,
+// and an FP32 sum leaves a rounding noise of a few 1e-7 in them that the
+// velocity shift tau F / rho multiplies by G tau (measured on the 32^3 droplet
+// box at tau = 3: 3e-5 density error after 500 steps with FP32 sums, 3.6e-6 with
+// FP64 sums).
+//
 // Instruction economy (the kernel issues about as many VALU instructions as it
 // can hide behind HBM traffic): populations are handled in opposite-velocity
 // pairs (c_{2k} = -c_{2k-1}), which shares the symmetric and antisymmetric parts
@@ -94,6 +103,63 @@ __device__ __forceinline__ void eq_pair(R cu, R aa, R rho3, R rho45, R &plus, R 
     minus = sym - asym;
 }
 
+// Weighted equilibria w_i g_eq,i (Sec. 2 Eq. 8) of the nine opposite pairs and of
+// the rest population, handed to push(i, value) in a fixed order; aa = rho (1 -
+// 3/2 u^2), r3 = 3 rho, r45 = 9/2 rho.  In FP64 the pairs go in order 1..9.  In
+// FP32 the rounded weights make the first moment of the equilibrium
+// 3 (w_1 + 4 w_2) rho u = rho u (1 + 3e-8) instead of rho u; a collision would then
+// scale the momentum of every node by that factor at every step (about 1e-5 of
+// the densities after 500 steps of the droplet box).  There the face diagonals go
+// first and the antisymmetric part of each axis pair is taken as rho u_a / 2
+// minus the diagonals' with c_a != 0, so that the first moment is rho u up to
+// one rounding (the same equilibrium in exact arithmetic).
+template <typename C, typename Push>
+__device__ __forceinline__ void equilibrium_pairs(C ux, C uy, C uz, C r, C aa, C r3, C r45, Push &&push) {
+    if constexpr (sizeof(C) == 8) {
+#pragma unroll
+        for (int p = 1; p <= 9; ++p) {
+            const int i = 2 * p - 1;
+            C cu = C(0);
+            if (cx_of(i)) cu += C(cx_of(i)) * ux;
+            if (cy_of(i)) cu += C(cy_of(i)) * uy;
+            if (cz_of(i)) cu += C(cz_of(i)) * uz;
+            C fplus, fminus;
+            eq_pair<C>(cu, aa, r3, r45, fplus, fminus);
+            push(i, w_of<C>(i) * fplus);
+            push(i + 1, w_of<C>(i) * fminus);
+        }
+    } else {
+        C mx = C(0), my = C(0), mz = C(0);  // sum over diagonals of c_a times the antisymmetric part
+#pragma unroll
+        for (int p = 4; p <= 9; ++p) {
+            const int i = 2 * p - 1;
+            C cu = C(0);
+            if (cx_of(i)) cu += C(cx_of(i)) * ux;
+            if (cy_of(i)) cu += C(cy_of(i)) * uy;
+            if (cz_of(i)) cu += C(cz_of(i)) * uz;
+            const C sym = w_of<C>(i) * ((r45 * cu) * cu + aa);
+            const C asym = w_of<C>(i) * (r3 * cu);
+            if (cx_of(i)) mx += C(cx_of(i)) * asym;
+            if (cy_of(i)) my += C(cy_of(i)) * asym;
+            if (cz_of(i)) mz += C(cz_of(i)) * asym;
+            push(i, sym + asym);
+            push(i + 1, sym - asym);
+        }
+        const C half = C(0.5) * r;
+        const C ua[3] = {ux, uy, uz}, ma[3] = {mx, my, mz};
+#pragma unroll
+        for (int p = 1; p <= 3; ++p) {
+            const int i = 2 * p - 1;
+            const C u = ua[p - 1];
+            const C sym = w_of<C>(i) * ((r45 * u) * u + aa);
+            const C asym = half * u - ma[p - 1];
+            push(i, sym + asym);
+            push(i + 1, sym - asym);
+        }
+    }
+    push(0, w_of<C>(0) * aa);
+}
+
 // The ten directions with c_x != 0 have slots j = 0..9 in the x-exchange
 // buffer (odd directions c_x = +1, even ones -1).
 constexpr int NXD = 10;
@@ -107,6 +173,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     using B = typename Prec<P>::B;
     using L = typename Prec<P>::L;
     using C = R;  // collision arithmetic
+    using D = typename Prec<P>::D;  // densities of the force stencil
     constexpr int TXW = 64 * WX;  // tile width: WX wavefronts per row
     constexpr int LW = TXW + 2;   // with the ring
     constexpr uint32_t EB = sizeof(S);
@@ -114,7 +181,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     // that nothing waits for them during the collision) are loaded while the
     // current one collides.  FP64 windows leave no registers for a third plane.
     constexpr bool PREFETCH = sizeof(S) < 8;
-    __shared__ R lds[4][2][TY + 2][LW];
+    __shared__ D lds[4][2][TY + 2][LW];
     // x exchange: post-collision values with c_x != 0, by component, slot, row and
     // column lx + 1; columns 0 and tw + 1 hold what streams in across the tile's
     // left and right edges (ghost populations, or the periodic wrap)
@@ -174,6 +241,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     const __half *ref_in = DEV ? a.ref_src + (int64_t)box * 2 * N : nullptr;
     __half *ref_out = DEV ? a.ref_dst + (int64_t)box * 2 * N : nullptr;
     const R rhob[2] = {R(a.rho_b[0]), R(a.rho_b[1])};
+    const D rhobd[2] = {D(a.rho_b[0]), D(a.rho_b[1])};
     // velocity gradient of step n (ghost mode), read before the first store so
     // that the reads are uniform scalar loads (no wait on the vector-memory queue)
     R Am[9];
@@ -289,13 +357,13 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             ring_nd = uint32_t(gz) * nxy + uint32_t(gy) * uint32_t(nx) + uint32_t(gx);
         }
         if (valid) {
-            const R r0 = own_in ? pair_density<R>(fcur[0]) : rhob[0];
-            const R r1 = own_in ? pair_density<R>(fcur[1]) : rhob[1];
+            const D r0 = own_in ? pair_density<D>(fcur[0]) : rhobd[0];
+            const D r1 = own_in ? pair_density<D>(fcur[1]) : rhobd[1];
             lds[slot][0][ly + 1][lx + 1] = r0;
             lds[slot][1][ly + 1][lx + 1] = r1;
         }
         if (ring_on) {
-            R rr[2] = {rhob[0], rhob[1]};
+            D rr[2] = {rhobd[0], rhobd[1]};
             if (ring_in) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
@@ -304,7 +372,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
 #pragma unroll
                     for (int i = 0; i < Q; ++i)
                         f[i] = Prec<P>::bload(rs[s], ring_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * ref);
-                    rr[s] = pair_density<R>(f);
+                    rr[s] = pair_density<D>(f);
                 }
             }
             lds[slot][0][rsy][rsx] = rr[0];
@@ -332,26 +400,27 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 R d[10];
 #pragma unroll
                 for (int p = 1; p <= 9; ++p) d[p] = R(f[s][2 * p - 1]) - R(f[s][2 * p]);
-                rho[s] = pair_density<R>(f[s]);
+                // the density summed when the plane was loaded (same value)
+                rho[s] = R(lds[sl(0)][s][ly + 1][lx + 1]);
                 j[s][0] = d[1] + d[4] + d[5] + d[6] + d[7];
                 j[s][1] = d[2] + d[4] - d[5] + d[8] + d[9];
                 j[s][2] = d[3] + d[6] - d[7] + d[8] - d[9];
             }
             // pair force, Eq. 7, as the stencil sum sig_s = sum_i w_i rho_s'(x + c_i) c_i
             // (F_s = -G rho_s sig_s) from pair differences of the LDS densities
-            R sig[2][3];
+            D sig[2][3];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const int o = 1 - s;
-                R e[10];
+                D e[10];
 #pragma unroll
                 for (int p = 1; p <= 9; ++p) {
                     const int i = 2 * p - 1;
-                    const R hi = lds[sl(cz_of(i))][o][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)];
-                    const R lo = lds[sl(-cz_of(i))][o][ly + 1 - cy_of(i)][lx + 1 - cx_of(i)];
+                    const D hi = lds[sl(cz_of(i))][o][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)];
+                    const D lo = lds[sl(-cz_of(i))][o][ly + 1 - cy_of(i)][lx + 1 - cx_of(i)];
                     e[p] = hi - lo;
                 }
-                const R w1 = R(1) / R(18), w2 = R(1) / R(36);
+                const D w1 = D(1) / D(18), w2 = D(1) / D(36);
                 sig[s][0] = w1 * e[1] + w2 * (e[4] + e[5] + e[6] + e[7]);
                 sig[s][1] = w1 * e[2] + w2 * (e[4] - e[5] + e[8] + e[9]);
                 sig[s][2] = w1 * e[3] + w2 * (e[6] - e[7] + e[8] - e[9]);
@@ -364,10 +433,18 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 const C om = C(s ? om1 : om0);
-                const R gt = R(a.g) * R(a.tau[s]);
-                const C ux = C(up[0] - gt * sig[s][0]);
-                const C uy = C(up[1] - gt * sig[s][1]);
-                const C uz = C(up[2] - gt * sig[s][2]);
+                const D gt = D(a.g) * D(a.tau[s]);
+                C ux, uy, uz;
+                if constexpr (sizeof(D) > sizeof(C)) {
+                    // FP32 arithmetic: the shift from the FP64 stencil sum, rounded once
+                    ux = C(up[0]) - C(gt * sig[s][0]);
+                    uy = C(up[1]) - C(gt * sig[s][1]);
+                    uz = C(up[2]) - C(gt * sig[s][2]);
+                } else {
+                    ux = C(up[0] - gt * sig[s][0]);
+                    uy = C(up[1] - gt * sig[s][1]);
+                    uz = C(up[2] - gt * sig[s][2]);
+                }
                 const C usq = ux * ux + uy * uy + uz * uz;
                 const C r = C(rho[s]);
                 const C aa = r - C(1.5) * r * usq;
@@ -379,9 +456,9 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 // exact arithmetic).
                 constexpr bool BALANCE = sizeof(C) == 4;
                 C psum = C(0);
-                auto push = [&](int i, C feq_i) {
+                auto push = [&](int i, C geq) {
                     const C fi = C(f[s][i]);
-                    C pst = fi + om * (w_of<C>(i) * feq_i - fi);
+                    C pst = fi + om * (geq - fi);
                     if (BALANCE) {
                         if (i == 0) pst = C(rho[s]) - psum;
                         else psum += pst;
@@ -416,19 +493,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     Prec<P>::bstore_bits(rd[s], dvo, 0, bits);
                 };
                 if (DEV) ref_store(ref_out + s * N + node, float(rho[s]));
-#pragma unroll
-                for (int p = 1; p <= 9; ++p) {
-                    const int i = 2 * p - 1;
-                    C cu = C(0);
-                    if (cx_of(i)) cu += C(cx_of(i)) * ux;
-                    if (cy_of(i)) cu += C(cy_of(i)) * uy;
-                    if (cz_of(i)) cu += C(cz_of(i)) * uz;
-                    C fplus, fminus;
-                    eq_pair<C>(cu, aa, r3, r45, fplus, fminus);
-                    push(i, fplus);
-                    push(i + 1, fminus);
-                }
-                push(0, aa);
+                equilibrium_pairs<C>(ux, uy, uz, r, aa, r3, r45, push);
             }
         }
         if (GHOST && y < ny) {

@@ -303,13 +303,13 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
                     const C r3 = C(3) * r, r45 = C(4.5) * r;
                     // FP32 arithmetic: the rest population closes the mass balance (as in k_step)
                     C psum = C(0);
-                    auto push = [&](int i, C feq_i) {
+                    auto push = [&](int i, C geq) {
                         // decoded again here rather than kept from the moments (registers);
                         // the empty asm keeps the compiler from reusing the first decode
                         uint32_t raw = fprev[s][i];
                         asm volatile("" : "+v"(raw));
                         const C fi = C(Prec<P>::dec(half_of(raw, j), w_of<R>(i) * rref[s]));
-                        C pst = fi + om * (w_of<C>(i) * feq_i - fi);
+                        C pst = fi + om * (geq - fi);
                         if (i == 0) pst = C(rho[s]) - psum;
                         else psum += pst;
                         const C dref = C(ref_round(float(lds[sl(cz_of(i))][s][ly + 1 + cy_of(i)][1 + nn + cx_of(i)])));
@@ -320,19 +320,7 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
                             if (cx_of(i) < 0 && nn == 0) xq[s][i][ly][tw + 1] = bits;
                         }
                     };
-#pragma unroll
-                    for (int p = 1; p <= 9; ++p) {
-                        const int i = 2 * p - 1;
-                        C cu = C(0);
-                        if (cx_of(i)) cu += C(cx_of(i)) * ux;
-                        if (cy_of(i)) cu += C(cy_of(i)) * uy;
-                        if (cz_of(i)) cu += C(cz_of(i)) * uz;
-                        C fplus, fminus;
-                        eq_pair<C>(cu, aa, r3, r45, fplus, fminus);
-                        push(i, fplus);
-                        push(i + 1, fminus);
-                    }
-                    push(0, aa);
+                    equilibrium_pairs<C>(ux, uy, uz, r, aa, r3, r45, push);
                 }
             }
             // reference densities of the pair (as ref_store rounds them)

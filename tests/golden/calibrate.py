@@ -16,8 +16,16 @@ model once the relaxation time (tau = 1, Table 1) and the density pair (1.0 insi
   keeps the ghost density constant and chosen to suit the droplet (Sec. 3); these
   values are that choice here.
 
-Writes ``calibration.json`` next to this file.  Run from the repository root:
-``python tests/golden/calibrate.py``.
+Writes ``calibration.json`` (tau = 1) next to this file.  Run from the
+repository root: ``python tests/golden/calibrate.py``.
+
+``--tau T --g G`` measures the same quantities at another relaxation time for a
+given coupling (no bisection; droplets start at the slab's coexisting densities)
+and writes ``calibration_tau<T>.json``.  At tau = 3 (Table 2) the single-rate
+model with the velocity-shift coupling reaches no stable droplet: a slab gives
+the ratios 0.065, 0.056, 0.047 at G = 3.0, 3.2, 3.4 and overflows at G = 3.6, and
+at G = 2.4 (ratio 0.12) droplets at rest carry spurious currents of about 0.15,
+so the Laplace fit there is meaningless.
 """
 from __future__ import annotations
 
@@ -52,25 +60,26 @@ def slab_coexistence(g: float, tau: float = TAU, nx: int = 64, steps: int = 3000
     return float(fa[0, 0, nx // 2]), float(fb[0, 0, nx // 2]), float(np.abs(u).max())
 
 
-def calibrate_g(lo: float = 1.5, hi: float = 1.8, iters: int = 14):
+def calibrate_g(lo: float = 1.5, hi: float = 1.8, iters: int = 14, tau: float = TAU):
     """Bisection on G so that minority/majority = 0.04 (ratio falls as G grows)."""
     for _ in range(iters):
         mid = 0.5 * (lo + hi)
-        a, b, _ = slab_coexistence(mid)
+        a, b, _ = slab_coexistence(mid, tau)
         if b / a > TARGET_RATIO:
             lo = mid
         else:
             hi = mid
     g = round(0.5 * (lo + hi), 4)
-    a, b, umax = slab_coexistence(g)
+    a, b, umax = slab_coexistence(g, tau)
     return g, a, b, umax
 
 
-def laplace(g: float, L: int = 32, radii=(6, 7, 8, 9, 10), steps: int = 3000):
+def laplace(g: float, L: int = 32, radii=(6, 7, 8, 9, 10), steps: int = 3000, tau: float = TAU,
+            rho_hi: float = RHO_HI, rho_lo: float = RHO_LO):
     rows = []
     for R in radii:
-        o = oracle.Oracle(L, L, L, periodic=True, tau=(TAU, TAU), g=g, rho_b=(RHO_LO, RHO_HI))
-        o.init_droplet([(L - 1) / 2.0] * 3, R, 2.0, RHO_HI, RHO_LO, None)
+        o = oracle.Oracle(L, L, L, periodic=True, tau=(tau, tau), g=g, rho_b=(rho_lo, rho_hi))
+        o.init_droplet([(L - 1) / 2.0] * 3, R, 2.0, rho_hi, rho_lo, None)
         o.run(steps)
         ra, rb, _ = o.fields()
         st = oracle.droplet_stats(ra, rb, o.xc)
@@ -94,17 +103,30 @@ def laplace(g: float, L: int = 32, radii=(6, 7, 8, 9, 10), steps: int = 3000):
 
 
 def main():
-    print("calibrating G_AB (flat interface, tau=%g)" % TAU, flush=True)
-    g, a, b, umax = calibrate_g()
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--tau", type=float, default=TAU)
+    ap.add_argument("--g", type=float, default=0.0, help="take this coupling instead of bisecting for 0.04")
+    args = ap.parse_args()
+    tau = args.tau
+    if args.g > 0:
+        g = args.g
+        a, b, umax = slab_coexistence(g, tau)
+        rho_hi, rho_lo = a, b
+    else:
+        print("calibrating G_AB (flat interface, tau=%g)" % tau, flush=True)
+        g, a, b, umax = calibrate_g(tau=tau)
+        rho_hi, rho_lo = RHO_HI, RHO_LO
     print("  G_AB=%.4f  bulk=(%.6f, %.6f)  ratio=%.5f" % (g, a, b, b / a), flush=True)
     print("Laplace law", flush=True)
-    lap = laplace(g)
+    lap = laplace(g, tau=tau, rho_hi=rho_hi, rho_lo=rho_lo)
     print("  sigma=%.6f  intercept=%.3g  R^2=%.6f" % (lap["sigma"], lap["intercept"], lap["r2"]), flush=True)
-    out = dict(tau=TAU, rho_hi=RHO_HI, rho_lo=RHO_LO, g_ab=g,
+    out = dict(tau=tau, rho_hi=rho_hi, rho_lo=rho_lo, g_ab=g,
                coexistence=dict(majority=a, minority=b, ratio=b / a, max_speed=umax),
                sigma=lap["sigma"], far_field_a=lap["far_field_a"], far_field_b=lap["far_field_b"],
                laplace=lap)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "calibration.json")
+    name = "calibration.json" if tau == 1.0 and args.g <= 0 else "calibration_tau%g.json" % tau
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name)
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print("wrote", path)

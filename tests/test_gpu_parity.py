@@ -27,15 +27,15 @@ def sc():
 
 
 def make_pair(sc, n, *, prec="f64", bc="ghost", R=6.0, A=None, steps=0, nxyz=None, g=wl.G_AB, tau=(1.0, 1.0),
-              mach_max=0.0):
+              mach_max=0.0, rho_in=wl.RHO_HI, rho_out=wl.RHO_LO, rho_b=None):
     nx, ny, nz = nxyz or (n, n, n)
-    rho_b = wl.ghost_densities(R)
+    rho_b = wl.ghost_densities(R) if rho_b is None else rho_b
     lat = sc.Lattice(nx, ny, nz, bc=bc, prec=prec, table_len=max(steps, 1), tau=tau, g_ab=g, rho_b=rho_b,
                      mach_max=mach_max)
     o = oracle.Oracle(nx, ny, nz, periodic=(bc == "periodic"), tau=tau, g=g, rho_b=rho_b)
     ctr = lat.xc
-    lat.init_droplet(ctr, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
-    o.init_droplet(ctr, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A)
+    lat.init_droplet(ctr, R, wl.WIDTH, rho_in, rho_out, A)
+    o.init_droplet(ctr, R, wl.WIDTH, rho_in, rho_out, A)
     return lat, o
 
 
@@ -45,12 +45,29 @@ def rel_density_error(lat, o, box=0):
     return max(np.max(np.abs(ra - oa) / np.abs(oa)), np.max(np.abs(rb - ob) / np.abs(ob)))
 
 
+# Relaxation times of the parity runs: tau = 1 (Table 1), where the collision
+# replaces every population by its equilibrium; tau = 3 for both phases, the
+# setting of Table 2 (with the coupling and interface densities of wl.TAU3; the
+# deformed droplet of this run amplifies a relative perturbation of the
+# populations about tenfold over the 500 steps, measured with the oracle); and
+# unequal relaxation times, which weight the common velocity u' by 1/tau per
+# component.  Away from tau = 1 the post-collision value depends on the incoming
+# population, so a mixed-up relaxation rate, a missing tau in the velocity shift
+# or a wrongly indexed population fails.
+T3 = wl.TAU3
+TAU_CASES = {"tau1": dict(tau=(1.0, 1.0)),
+             "tau3": dict(tau=(3.0, 3.0), g=T3["g_ab"], rho_in=T3["rho_hi"], rho_out=T3["rho_lo"],
+                          rho_b=(T3["rho_lo"], T3["rho_hi"])),
+             "tau0.8_1.4": dict(tau=(0.8, 1.4))}
+
+
+@pytest.mark.parametrize("taucase", list(TAU_CASES))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_c1_droplet_shear_parity_500_steps(sc, prec):
+def test_c1_droplet_shear_parity_500_steps(sc, prec, taucase):
     case = wl.case_c1()
     A = case.tables[0][0]
     steps = 500
-    lat, o = make_pair(sc, 32, prec=prec, R=case.radius, A=A, steps=steps, mach_max=0.25)
+    lat, o = make_pair(sc, 32, prec=prec, R=case.radius, A=A, steps=steps, mach_max=0.25, **TAU_CASES[taucase])
     tab = case.tables[0][:steps]
     lat.set_gradient_table(tab, 0)
     lat.step(steps)
@@ -79,6 +96,57 @@ def test_c1_droplet_shear_parity_500_steps(sc, prec):
     e_gpu = lat.velocity_error(A)
     e_ref = oracle.velocity_error(ou, A, o.xc)
     assert abs(e_gpu - e_ref) <= (1e-11 if prec == "f64" else 1e-4) * e_ref
+    # FP64 totals (mass per component, momentum) against the oracle's sums
+    m, p = lat.totals()
+    om, op = o.totals()
+    assert np.all(np.abs(m - om) / om <= TOT_TOL[prec])
+    assert np.abs(p - op).max() <= TOT_TOL[prec] * om.sum() * np.abs(ou).max()
+
+
+# Totals: FP64 sums over every node of the per-node densities and momenta.  In
+# FP64 storage the per-node values agree with the oracle to ~1e-15 relative, so
+# the sums do to ~1e-13; in FP32 storage to the per-node bound above.
+TOT_TOL = {"f64": 1e-12, "f32": 1e-6}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("bc", ["ghost", "periodic"])
+def test_totals_with_momentum_match_oracle(sc, prec, bc):
+    """An off-centre droplet whose fluid moves with a uniform velocity on top of
+    the imposed flow, so that the total momentum is far from zero: in ghost
+    mode the open boundary changes mass and momentum (driven by a
+    non-symmetric gradient), in periodic mode both are conserved.  Totals
+    against the oracle's after 200 steps, unequal relaxation times."""
+    n, R, steps = 24, 5.0, 200
+    rho_b = wl.ghost_densities(R)
+    tau = (1.0, 1.3)
+    lat = sc.Lattice(n, n, n, bc=bc, prec=prec, table_len=steps, tau=tau, g_ab=wl.G_AB, rho_b=rho_b)
+    o = oracle.Oracle(n, n, n, periodic=(bc == "periodic"), tau=tau, g=wl.G_AB, rho_b=rho_b)
+    ctr = np.array(lat.xc) + np.array([2.5, -1.5, 1.0])
+    o.init_droplet(ctr, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, None)
+    ra, rb, _ = o.fields()  # the tanh profile, as FP64 fields for both sides
+    u0 = np.array([0.03, -0.02, 0.015])
+    A = np.array([0.0005, 0.0, 0.0021, 0.0004, -0.0009, 0.0, 0.0012, -0.0006, 0.0004])
+    u = np.broadcast_to(u0[:, None, None, None], (3,) + ra.shape).copy()
+    if bc == "ghost":
+        z, y, x = np.meshgrid(*(np.arange(k) - c for k, c in zip(ra.shape, lat.xc[::-1])), indexing="ij")
+        d = np.stack([x, y, z])
+        u += np.einsum("ij,jzyx->izyx", A.reshape(3, 3), d)
+    o.init_fields(ra, rb, u)
+    lat.init_fields(ra, rb, u)
+    tab = np.tile(A, (steps, 1))
+    if bc == "ghost":
+        lat.set_gradient_table(tab, 0)
+        o.run(steps, tab)
+    else:
+        o.run(steps)
+    lat.step(steps)
+    m, p = lat.totals()
+    om, op = o.totals()
+    print("%s %s: mass %s vs %s, momentum %s vs %s" % (prec, bc, m, om, p, op))
+    assert np.abs(op).max() > 1.0  # the momentum is far from zero
+    assert np.all(np.abs(m - om) / om <= TOT_TOL[prec])
+    assert np.abs(p - op).max() <= TOT_TOL[prec] * np.abs(op).max() * 10
 
 
 @pytest.mark.parametrize("bc", ["ghost", "periodic"])
