@@ -172,6 +172,19 @@ sclbm_status sclbm_droplet_moments(sclbm_ctx *ctx, int32_t box, double *dev_out1
  * Does not synchronise. */
 sclbm_status sclbm_droplet_moments_all(sclbm_ctx *ctx, double *dev_out);
 
+/* sclbm_droplet_moments_all without the workspace's reduction area, for callers
+ * that cannot allocate device memory or size a workspace for it (code under HIP
+ * graph capture, tight serving loops).  The partial sums and per-box results live
+ * in a static device array of 2 MiB that the library holds on every GPU it runs
+ * on until the process ends; a context of nbox boxes needs
+ * nbox * (blocks per box + 1) * 16 doubles of it (blocks per box: about one per
+ * 2048 nodes, at least 1024 / nbox, at most 1024), else ESIZE and nothing is
+ * launched (64 boxes of 64^3 use 1.0 MiB).  Same kernels and results as
+ * sclbm_droplet_moments_all, bit for bit.  Allocates nothing.  Calls that overlap
+ * on one GPU (several streams or host threads) share the array and race; each
+ * call overwrites what it reads before reading it.  Does not synchronise. */
+sclbm_status sclbm_droplet_moments_all_static(sclbm_ctx *ctx, double *dev_out);
+
 /* Droplet statistics from 10 indicator moments about `center` (host only, no
  * GPU work): covariance, its eigenvalues by the closed-form trigonometric
  * method for symmetric 3x3 matrices, semi-axes, deformation (Sec. 2 Eq. 4). */

@@ -54,6 +54,7 @@ EXPORTS = [
     "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch", "sclbm_default_launch",
     "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune", "sclbm_droplet_moments_all", "sclbm_mm_integrate",
     "sclbm_droplet_surface_all", "sclbm_deformation_lbm", "sclbm_droplet_mass_all", "sclbm_reinject",
+    "sclbm_droplet_moments_all_static",
     # droplet-shape surrogate (sclmlp.h)
     "sclmlp_workspace_bytes", "sclmlp_create", "sclmlp_destroy", "sclmlp_set_params", "sclmlp_get_params",
     "sclmlp_get_grads", "sclmlp_set_normalization", "sclmlp_predict", "sclmlp_gradients", "sclmlp_adam",
@@ -90,6 +91,7 @@ def _load_library():
         "sclbm_totals": [P, I32, dp, dp],
         "sclbm_droplet_moments": [P, I32, P],
         "sclbm_droplet_moments_all": [P, P],
+        "sclbm_droplet_moments_all_static": [P, P],
         "sclbm_droplet_surface_all": [P, P],
         "sclbm_deformation_lbm": [D, D, dp],
         "sclbm_droplet_mass_all": [P, P],
@@ -239,6 +241,10 @@ def sclbm_droplet_moments(ctx, box, dev_out_ptr):
 
 def sclbm_droplet_moments_all(ctx, dev_out_ptr):
     _check(_lib.sclbm_droplet_moments_all(ctx, ctypes.c_void_p(dev_out_ptr)))
+
+
+def sclbm_droplet_moments_all_static(ctx, dev_out_ptr):
+    _check(_lib.sclbm_droplet_moments_all_static(ctx, ctypes.c_void_p(dev_out_ptr)))
 
 
 def sclbm_droplet_surface_all(ctx, dev_out_ptr):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -113,6 +114,37 @@ Layout make_layout(const sclbm_config *c) {
 
 }  // namespace
 
+// Device memory of the allocation-free droplet moments
+// (sclbm_droplet_moments_all_static): the statistics partials and per-box
+// results.  Every GPU the library runs on holds its own copy until the process
+// ends.  In host code `scratch` names no device address; the address on a
+// device comes from hipGetSymbolAddress with that device current.
+constexpr size_t kScratchDoubles = size_t(1) << 18;  // 2 MiB
+__device__ __align__(256) static double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev`, resolved once per device; `dev` must be
+// the current device.
+sclbm_status scratch_address(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(SCLBM_EINVAL, "device %d out of range [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(SCLBM_EHIP, "no device address for the static scratch on device %d", dev);
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return SCLBM_OK;
+}
+
+}  // namespace
+
 struct sclbm_ctx {
     sclbm_config cfg;
     Layout lay;
@@ -130,6 +162,7 @@ struct sclbm_ctx {
     int graph_par = -1, graph_ty = 0, graph_wx = 0, graph_zc = 0;
     int64_t N;
     BoxGeom geom;
+    int device = 0;   // HIP device current at create
 
     void *fbuf(int which) { return ws + (which ? lay.f1 : lay.f0); }
     __half *refbuf(int which) {
@@ -378,18 +411,22 @@ sclbm_status reduce_final(sclbm_ctx *c, int nblk, double *host_out) {
 
 // Launch the FP64 statistics of boxes [b0, b0 + nb) at time n; the final 16
 // values of box b0 + i go to c->result() + 16 i (device).
-sclbm_status launch_stats(sclbm_ctx *c, int32_t b0, int32_t nb) {
+// Partials [box][block][16] go to `partial` (nb * stats_blocks * 16 doubles) and
+// the final values to `result` (nb * 16); by default the workspace's areas.
+sclbm_status launch_stats(sclbm_ctx *c, int32_t b0, int32_t nb, double *partial = nullptr, double *result = nullptr) {
     const int bpb = int(stats_blocks(&c->cfg));
+    if (!partial) partial = c->partial();
+    if (!result) result = c->result();
     hipError_t e = by_prec(c->cfg.prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
         using S = typename Prec<P>::S;
         const S *f = reinterpret_cast<const S *>(c->fbuf(c->par));
         hipLaunchKernelGGL((k_stats<P>), dim3(bpb, nb), dim3(NRED_THREADS), 0, c->stream, f, c->refbuf(c->par),
-                           c->geom, b0, c->partial());
+                           c->geom, b0, partial);
         return hipGetLastError();
     });
     if (e != hipSuccess) return fail(SCLBM_EHIP, "stats kernel: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL((k_final<NSTAT>), dim3(nb), dim3(NRED_THREADS), 0, c->stream, c->partial(), bpb, c->result());
+    hipLaunchKernelGGL((k_final<NSTAT>), dim3(nb), dim3(NRED_THREADS), 0, c->stream, partial, bpb, result);
     HIP_LAUNCHED();
     return SCLBM_OK;
 }
@@ -468,6 +505,17 @@ sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t b
     if (!c) return fail(SCLBM_EINVAL, "host allocation failed");
     c->cfg = *cfg;
     c->lay = lay;
+    {
+        // the static scratch's address on this device, resolved here with the device current
+        double *unused = nullptr;
+        sclbm_status st = SCLBM_OK;
+        if (hipGetDevice(&c->device) != hipSuccess) st = fail(SCLBM_EHIP, "hipGetDevice failed");
+        if (st == SCLBM_OK) st = scratch_address(c->device, &unused);
+        if (st != SCLBM_OK) {
+            delete c;
+            return st;
+        }
+    }
     c->ws = static_cast<char *>(dev_workspace);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->n = 0;
@@ -806,6 +854,25 @@ sclbm_status sclbm_droplet_moments_all(sclbm_ctx *c, double *dev_out) {
     if ((st = launch_stats(c, 0, c->cfg.nbox))) return st;
     HIP_TRY(hipMemcpy2DAsync(dev_out, 10 * sizeof(double), c->result() + 5, NSTAT * sizeof(double), 10 * sizeof(double),
                              size_t(c->cfg.nbox), hipMemcpyDeviceToDevice, c->stream));
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_droplet_moments_all_static(sclbm_ctx *c, double *dev_out) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (!dev_out) return fail(SCLBM_EINVAL, "null output");
+    const size_t nb = size_t(c->cfg.nbox), bpb = stats_blocks(&c->cfg);
+    const size_t need = nb * (bpb + 1) * NSTAT;
+    if (need > kScratchDoubles)
+        return fail(SCLBM_ESIZE, "%zu boxes need %zu doubles of static scratch; it holds %zu (%zu boxes of this size)",
+                    nb, need, kScratchDoubles, kScratchDoubles / ((bpb + 1) * NSTAT));
+    double *s = nullptr;
+    if ((st = scratch_address(c->device, &s))) return st;
+    // every partial and result slot read below is written first by this call's kernels
+    double *partial = s, *result = s + nb * bpb * NSTAT;
+    if ((st = launch_stats(c, 0, c->cfg.nbox, partial, result))) return st;
+    HIP_TRY(hipMemcpy2DAsync(dev_out, 10 * sizeof(double), result + 5, NSTAT * sizeof(double), 10 * sizeof(double),
+                             nb, hipMemcpyDeviceToDevice, c->stream));
     return SCLBM_OK;
 }
 
