@@ -29,6 +29,7 @@ SIGMA = 0.089909     # Laplace law, tau = 1, G_AB above
 FAR_FIELD_A = (0.05375933605501905, 0.04041950406144379)    # rho_A far field = a/R_eq + b
 FAR_FIELD_B = (-0.235900760858221, 1.0375176769822088)      # rho_B far field = a/R_eq + b
 CS = 1.0 / math.sqrt(3.0)
+MACH_MAX = 0.2       # Sec. 4: the velocity scale keeps Ma <= 0.2
 
 
 # tau = 3 for both phases (Table 2), coupling G = 2.4, and the densities a flat
