@@ -205,8 +205,11 @@ def main():
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     ap.add_argument("--format-steps", type=int, default=0,
-                    help="only run this many steps of the 128^3 box in FP32 and in FP64 storage, default launch "
+                    help="only run this many steps of the droplet box in each of --formats, default launch "
                          "(for per-kernel counter runs)")
+    ap.add_argument("--format-box", type=int, default=128, help="box of --format-steps: 128 (OU seed 2) or 256 "
+                    "(OU seed 3)")
+    ap.add_argument("--formats", type=str, default="f32,f64", help="storage formats of --format-steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs the hot path on a single MI355X "
@@ -230,9 +233,12 @@ def main():
         precision_study(sc, args.c3_steps)
         return
     if args.format_steps > 0:
-        case = wl.case_c2(nsteps=args.format_steps + 1)
+        if args.format_box == 256:
+            case = wl.case_c3(nsteps=args.format_steps + 1)
+        else:
+            case = wl.case_c2(nsteps=args.format_steps + 1)
         tab = case.tables[0]
-        for prec in ("f32", "f64"):
+        for prec in args.formats.split(","):
             lat = sc.Lattice(case.n, case.n, case.n, bc="ghost", prec=prec, table_len=args.format_steps,
                              g_ab=wl.G_AB, rho_b=case.rho_b, mach_max=wl.MACH_MAX)
             lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])

@@ -61,10 +61,11 @@ typedef enum {
 } sclbm_bc;
 
 typedef enum {
-    SCLBM_F64 = 0,    /* FP64 populations, FP64 arithmetic */
-    SCLBM_F32 = 1,    /* FP32 populations, FP32 arithmetic */
-    SCLBM_F16DEV = 2, /* FP16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
-    SCLBM_BF16DEV = 3 /* BF16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
+    SCLBM_F64 = 0,     /* FP64 populations, FP64 arithmetic */
+    SCLBM_F32 = 1,     /* FP32 populations, FP32 arithmetic (force-stencil densities summed in FP64) */
+    SCLBM_F16DEV = 2,  /* FP16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
+    SCLBM_BF16DEV = 3, /* BF16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
+    SCLBM_F32D = 4     /* FP32 populations, FP64 arithmetic: only the storage rounds (slower) */
 } sclbm_prec;
 
 typedef struct {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libsclbm.so")
 
 SCLBM_OK, SCLBM_EINVAL, SCLBM_ESIZE, SCLBM_EHIP, SCLBM_EUNSTABLE, SCLBM_ESTATE = 0, -1, -2, -3, -4, -5
 BC = {"periodic": 0, "ghost": 1}
-PREC = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3}
+PREC = {"f64": 0, "f32": 1, "f16dev": 2, "bf16dev": 3, "f32d": 4}
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESIZE", -3: "EHIP", -4: "EUNSTABLE", -5: "ESTATE"}
 
 

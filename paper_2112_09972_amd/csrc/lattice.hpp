@@ -52,13 +52,17 @@ __host__ __device__ constexpr R w_of(int i) {
 
 // Storage formats.  S is what lives in HBM, W the type a loaded population is
 // held in registers (exactly representable from S), R the arithmetic type.
-// FP32 storage computes in FP32.  The FP32-rounded lattice weights do not sum
-// to one (1 + 3e-8), so a single-rate collision written population by
-// population would create or destroy that much mass at every node and step
-// (2e-5 density error after 500 steps of the droplet box); the step kernel
-// therefore lets the rest population close the mass balance, rho minus the
-// other eighteen post-collision values, which is the same update in exact
-// arithmetic.
+// FP32 storage computes in FP32 (SCLBM_F32) or in FP64 (SCLBM_F32D).  The
+// FP32-rounded lattice weights do not sum to one (1 + 3e-8), so a single-rate
+// collision in FP32 written population by population would create or destroy
+// that much mass at every node and step (2e-5 density error after 500 steps of
+// the droplet box); the step kernel therefore lets the rest population close
+// the mass balance, rho minus the other eighteen post-collision values, which
+// is the same update in exact arithmetic.  With FP64 arithmetic the only
+// rounding is the storage's (1.1e-7 to 2.3e-7 after 500 steps of the droplet
+// box at tau = 1, 3 and (0.8, 1.4), against 6.7e-7, 2.2e-5 and 3.8e-6 in FP32
+// arithmetic; the tau = 3 run, with spurious currents of order 0.1, amplifies
+// the extra roundings most).
 // The deviation formats hold d_i = f_i / (w_i rho_ref(x)) - 1 in 16 bits with FP32
 // arithmetic, rho_ref(x) being the node's own density one step earlier, kept
 // per node and component in FP16 (DEV = true).  A constant reference fails in
@@ -120,12 +124,13 @@ struct Prec<SCLBM_F64> {
         bstore_bits(r, vo, so, enc(v, wref));
     }
 };
-template <>
-struct Prec<SCLBM_F32> {
+// FP32 storage; RT the arithmetic type (FP32 for SCLBM_F32, FP64 for SCLBM_F32D).
+template <typename RT>
+struct PrecF32 {
     static constexpr bool DEV = false;
     using S = float;
     using W = float;
-    using R = float;
+    using R = RT;
     using D = double;
     static __device__ __forceinline__ W load(const S *p, R /*wref*/) { return *p; }
     static __device__ __forceinline__ void store(S *p, R v, R /*wref*/) { *p = float(v); }
@@ -147,6 +152,10 @@ struct Prec<SCLBM_F32> {
         bstore_bits(r, vo, so, enc(v, wref));
     }
 };
+template <>
+struct Prec<SCLBM_F32> : PrecF32<float> {};
+template <>
+struct Prec<SCLBM_F32D> : PrecF32<double> {};
 template <>
 struct Prec<SCLBM_F16DEV> {
     static constexpr bool DEV = true;
@@ -223,7 +232,8 @@ inline bool is_dev(int prec) { return prec == SCLBM_F16DEV || prec == SCLBM_BF16
 inline size_t elem_bytes(int prec) {
     switch (prec) {
         case SCLBM_F64: return 8;
-        case SCLBM_F32: return 4;
+        case SCLBM_F32:
+        case SCLBM_F32D: return 4;
         default: return 2;
     }
 }

@@ -65,7 +65,7 @@ bool config_ok(const sclbm_config *c, std::string &why) {
     if (c->nx > 4096 || c->ny > 65535 || c->nz > 65535) { why = "box too large"; return false; }
     if (c->nbox < 1) { why = "nbox must be >= 1"; return false; }
     if (c->bc != SCLBM_BC_PERIODIC && c->bc != SCLBM_BC_GHOST) { why = "unknown boundary mode"; return false; }
-    if (c->prec < SCLBM_F64 || c->prec > SCLBM_BF16DEV) { why = "unknown precision"; return false; }
+    if (c->prec < SCLBM_F64 || c->prec > SCLBM_F32D) { why = "unknown precision"; return false; }
     if (!(c->tau[0] > 0.5) || !(c->tau[1] > 0.5)) { why = "tau must exceed 1/2"; return false; }
     if (!(c->rho_b[0] > 0.0) || !(c->rho_b[1] > 0.0)) { why = "rho_b must be positive"; return false; }
     if (!std::isfinite(c->g_ab)) { why = "g_ab must be finite"; return false; }
@@ -306,6 +306,7 @@ hipError_t launch_step_prec(sclbm_ctx *c, const StepArgs &a) {
     switch (c->cfg.prec) {
         case SCLBM_F64: return launch_step<SCLBM_F64>(c, a);
         case SCLBM_F32: return launch_step<SCLBM_F32>(c, a);
+        case SCLBM_F32D: return launch_step<SCLBM_F32D>(c, a);
         case SCLBM_F16DEV: return launch_step<SCLBM_F16DEV>(c, a);
         default: return launch_step<SCLBM_BF16DEV>(c, a);
     }
@@ -317,6 +318,7 @@ hipError_t by_prec(int prec, Fn &&fn) {
     switch (prec) {
         case SCLBM_F64: return fn(std::integral_constant<int, SCLBM_F64>{});
         case SCLBM_F32: return fn(std::integral_constant<int, SCLBM_F32>{});
+        case SCLBM_F32D: return fn(std::integral_constant<int, SCLBM_F32D>{});
         case SCLBM_F16DEV: return fn(std::integral_constant<int, SCLBM_F16DEV>{});
         default: return fn(std::integral_constant<int, SCLBM_BF16DEV>{});
     }

@@ -57,6 +57,37 @@ def test_ensemble_equals_independent_boxes(sc, launch):
     assert max(np.max(np.abs(ra - oa) / oa), np.max(np.abs(rb - ob) / ob)) <= 1e-11
 
 
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_ensemble_tau3_boxes_and_totals_match_oracle(sc, prec, tol):
+    """A 3-box ensemble at tau = 3 for both phases (Table 2; coupling and interface
+    densities of wl.TAU3), each box with its own drive: every box's densities and
+    FP64 totals (mass per component, momentum) against the oracle's after 40 steps."""
+    n, nbox, steps, R = 24, 3, 40, 5.0
+    T3 = wl.TAU3
+    rho_b = (T3["rho_lo"], T3["rho_hi"])
+    tabs = ou_tables(n, nbox, steps)
+    ens = sc.Lattice(n, n, n, nbox=nbox, bc="ghost", prec=prec, table_len=steps, tau=(3.0, 3.0), g_ab=T3["g_ab"],
+                     rho_b=rho_b)
+    for b in range(nbox):
+        ens.init_droplet(ens.xc + 0.7 * b, R, wl.WIDTH, T3["rho_hi"], T3["rho_lo"], tabs[b][0], box=b)
+        ens.set_gradient_table(tabs[b], 0, box=b)
+    ens.step(steps)
+    for b in range(nbox):
+        o = oracle.Oracle(n, n, n, periodic=False, tau=(3.0, 3.0), g=T3["g_ab"], rho_b=rho_b)
+        o.init_droplet(o.xc + 0.7 * b, R, wl.WIDTH, T3["rho_hi"], T3["rho_lo"], tabs[b][0])
+        o.run(steps, tabs[b])
+        ra, rb, _ = (t.cpu().numpy() for t in ens.fields(box=b))
+        oa, ob, _ = o.fields()
+        err = max(np.max(np.abs(ra - oa) / oa), np.max(np.abs(rb - ob) / ob))
+        print("%s box %d: max rel density error %.3e" % (prec, b, err))
+        assert err <= tol, b
+        m, p = ens.totals(box=b)
+        om, op = o.totals()
+        assert np.all(np.abs(m - om) / om <= 10 * tol), b
+        assert np.abs(p - op).max() <= 10 * tol * om.sum() * 0.05, b
+    ens.close()
+
+
 @pytest.mark.parametrize("prec,wide", [("f16dev", 2), ("bf16dev", 2), ("f16dev", 4)])
 def test_deviation_ensemble_two_node_tiles(sc, prec, wide):
     """16-bit formats on 128 x 4 or 256 x 4 tiles (two nodes per lane): every box of a

@@ -13,7 +13,14 @@ from paper_2112_09972_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f64": 1e-11, "f32": 1e-5}
+TOL = {"f64": 1e-11, "f32": 1e-5, "f32d": 1e-5}
+# FP32 storage with FP32 arithmetic at tau = 3 (the setting of Table 2, at which
+# this model's droplet carries spurious currents of order 0.1): the run amplifies
+# the arithmetic's extra roundings far more than at tau = 1.  A CPU emulation of
+# the kernel's FP32 arithmetic, with single parts moved to FP64 in turn, ends at
+# 1.7e-6 .. 4.3e-5 on such runs while FP32 storage alone gives 1.1e-7 to 7e-7,
+# so the bound there is 1e-4; FP32 storage with FP64 arithmetic (f32d) keeps 1e-5.
+TOL_F32_TAU3 = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +69,7 @@ TAU_CASES = {"tau1": dict(tau=(1.0, 1.0)),
 
 
 @pytest.mark.parametrize("taucase", list(TAU_CASES))
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32d"])
 def test_c1_droplet_shear_parity_500_steps(sc, prec, taucase):
     case = wl.case_c1()
     A = case.tables[0][0]
@@ -77,7 +84,7 @@ def test_c1_droplet_shear_parity_500_steps(sc, prec, taucase):
     oa, ob, ou = o.fields()
     err = max(np.max(np.abs(ra - oa) / oa), np.max(np.abs(rb - ob) / ob))
     print("%s: max rel density error %.3e" % (prec, err))
-    assert err <= TOL[prec]
+    assert err <= (TOL_F32_TAU3 if (prec, taucase) == ("f32", "tau3") else TOL[prec])
     assert np.max(np.abs(u - ou)) / np.max(np.abs(ou)) <= (1e-10 if prec == "f64" else 1e-4)
     # droplet statistics: same decision precision (oracle analysis of the GPU's own fields) is exact
     st = lat.droplet()
@@ -106,10 +113,10 @@ def test_c1_droplet_shear_parity_500_steps(sc, prec, taucase):
 # Totals: FP64 sums over every node of the per-node densities and momenta.  In
 # FP64 storage the per-node values agree with the oracle to ~1e-15 relative, so
 # the sums do to ~1e-13; in FP32 storage to the per-node bound above.
-TOT_TOL = {"f64": 1e-12, "f32": 1e-6}
+TOT_TOL = {"f64": 1e-12, "f32": 1e-6, "f32d": 1e-6}
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f32d"])
 @pytest.mark.parametrize("bc", ["ghost", "periodic"])
 def test_totals_with_momentum_match_oracle(sc, prec, bc):
     """An off-centre droplet whose fluid moves with a uniform velocity on top of
@@ -184,7 +191,7 @@ def test_launch_shape_does_not_change_bits(sc):
     assert all(np.array_equal(out[0][64:], o[64:]) for o in out[1:])
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "f16dev", "bf16dev"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16dev", "bf16dev", "f32d"])
 @pytest.mark.parametrize("bc,nx", [("ghost", 100), ("ghost", 150), ("periodic", 150)])
 def test_launch_shape_bits_every_format(sc, prec, bc, nx):
     """Every storage format gives the same bits at every tile shape: one-wavefront
@@ -366,6 +373,37 @@ def test_two_node_tiles_deviation_formats(sc, prec, bc, nxyz, launch):
             o.run(steps, tab if bc == "ghost" else None)
             err = rel_density_error(lat, o)
             print("%s %s %s: max rel density error %.3e" % (prec, bc, nxyz, err))
+            assert err <= DEV_TOL[prec]
+        lat.close()
+    assert np.array_equal(out[0][64:], out[1][64:])
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("bc,nxyz,launch", [("ghost", (150, 13, 11), (4, 5, 2)), ("periodic", (270, 6, 5), (4, 3, 4)),
+                                            ("ghost", (300, 6, 5), (4, 2, 4))])
+def test_two_node_tiles_deviation_formats_tau3(sc, prec, bc, nxyz, launch):
+    """The 16-bit formats at tau = 3 (Table 2; wl.TAU3), where every post-collision
+    value keeps two thirds of the incoming population, so that the pair kernel's
+    decode of f_i at the collision matters: against the oracle, and bit for bit
+    against 64-node tiles of one node per lane."""
+    A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
+    steps = 20
+    tab = np.tile(A, (steps, 1))
+    kw = dict(tau=(3.0, 3.0), g=T3["g_ab"], rho_in=T3["rho_hi"], rho_out=T3["rho_lo"],
+              rho_b=(T3["rho_lo"], T3["rho_hi"]))
+    out = []
+    for shape in (launch, (4, 3, 1)):
+        lat, o = make_pair(sc, None, nxyz=nxyz, prec=prec, bc=bc, R=4.0, A=A if bc == "ghost" else None,
+                           steps=steps, **kw)
+        lat.set_launch(*shape)
+        if bc == "ghost":
+            lat.set_gradient_table(tab, 0)
+        lat.step(steps)
+        out.append(lat.save())
+        if shape == launch:
+            o.run(steps, tab if bc == "ghost" else None)
+            err = rel_density_error(lat, o)
+            print("%s %s %s tau3: max rel density error %.3e" % (prec, bc, nxyz, err))
             assert err <= DEV_TOL[prec]
         lat.close()
     assert np.array_equal(out[0][64:], out[1][64:])
