@@ -121,9 +121,18 @@ sclbm_status sclbm_init_droplet(sclbm_ctx *ctx, int32_t box, const double center
                                 double width, double rho_in, double rho_out, const double A0[9]);
 
 /* Initial state of one box from FP64 device fields rho_a[N], rho_b[N], u[3][N]
- * (u may be NULL for rest): populations at equilibrium.  Resets the time to 0. */
+ * (u may be NULL for rest): populations at the equilibrium of Sec. 2 Eq. 8 of
+ * each node's densities and velocity (the densities and velocity of Eq. 6
+ * then reproduce the fields).  Resets the time to 0.  Errors: EINVAL (box,
+ * NULL density field).  The fields are read before the call returns. */
 sclbm_status sclbm_init_fields(sclbm_ctx *ctx, int32_t box, const double *rho_a, const double *rho_b,
                                const double *u);
+
+/* Initial state of one box (box = -1: every box): uniform densities rho_a,
+ * rho_b (> 0) moving with u0[3] (NULL: at rest), populations at the equilibrium
+ * of Sec. 2 Eq. 8.  A uniform bulk state is a fixed point of the update (the
+ * stationarity check of the method).  Resets the time to 0.  Errors: EINVAL. */
+sclbm_status sclbm_init_uniform(sclbm_ctx *ctx, int32_t box, double rho_a, double rho_b, const double u0[3]);
 
 /* Copy n rows of a box's velocity-gradient table from host memory: row t drives
  * step first_step + t (Sec. 3 Eq. 14; Sec. 4 holds each sample of the turbulent
@@ -134,9 +143,22 @@ sclbm_status sclbm_init_fields(sclbm_ctx *ctx, int32_t box, const double *rho_a,
 sclbm_status sclbm_set_gradient_table(sclbm_ctx *ctx, int32_t box, const double *A_rows, int64_t first_step,
                                       int64_t n);
 
-/* Advance every box by nsteps (fused stream-collide update, one kernel launch
- * per step).  In ghost mode every box's table must cover steps n..n+nsteps-1,
- * else ESTATE and nothing is launched. */
+/* A constant velocity gradient A[9] for one box (box = -1: every box), as in the
+ * steady simple shear of the validation of Sec. 4 (u = A (x - x_c), Sec. 3
+ * Eq. 14): fills the box's whole table, table_len rows, starting at the
+ * current time n, so the next table_len steps use A.  Same checks as
+ * sclbm_set_gradient_table (ESTATE in periodic mode, EINVAL for a non-finite
+ * entry or a ghost speed above mach_max c_s).  Synchronises. */
+sclbm_status sclbm_set_gradient(sclbm_ctx *ctx, int32_t box, const double A[9]);
+
+/* Advance every box by nsteps time steps of the method (Sec. 2 Eqs. 6-9: moments,
+ * pair force of Eq. 7, velocity shift, single-rate collision, streaming; ghost
+ * populations of Sec. 2 Eq. 8 at the faces with u = A(t)(x - x_c), Sec. 3
+ * Eq. 14), one fused kernel launch per step.  In ghost mode every box's table
+ * must cover steps n..n+nsteps-1, else ESTATE and nothing is launched.  With
+ * the health check on (sclbm_set_health_check), every time that is a multiple
+ * of its interval is checked, which synchronises; EUNSTABLE then stops the
+ * call at that time (the steps before it are done). */
 sclbm_status sclbm_step(sclbm_ctx *ctx, int64_t nsteps);
 
 /* Advance every box by nsteps through a captured hipGraph of nsteps fused
@@ -146,6 +168,14 @@ sclbm_status sclbm_step(sclbm_ctx *ctx, int64_t nsteps);
  * Same table rules as sclbm_step.  The graph is rebuilt after sclbm_set_launch
  * or when an odd number of eager steps changed the buffer parity. */
 sclbm_status sclbm_step_graph(sclbm_ctx *ctx, int64_t nsteps);
+
+/* Health check of the step calls: every `every` steps (0: off, the default)
+ * sclbm_step computes every box's FP64 mass and counts the nodes with a NaN/Inf
+ * or non-positive density (the same reduction as sclbm_totals) and returns
+ * EUNSTABLE naming the first bad box; sclbm_step_graph checks once after each
+ * replay.  Each check costs one read of every population.  Errors: EINVAL
+ * (every < 0). */
+sclbm_status sclbm_set_health_check(sclbm_ctx *ctx, int64_t every);
 
 /* Current time n. */
 sclbm_status sclbm_get_step(const sclbm_ctx *ctx, int64_t *step);
@@ -158,15 +188,21 @@ sclbm_status sclbm_get_step(const sclbm_ctx *ctx, int64_t *step);
 sclbm_status sclbm_fields(sclbm_ctx *ctx, int32_t box, double *rho_a, double *rho_b, double *u);
 
 /* FP64 totals of one box at time n: mass[2] = sum rho_A, sum rho_B and
- * momentum[3] = sum (j_A + j_B).  Deterministic fixed-order reduction.
- * Synchronises the stream.  EUNSTABLE if a NaN/Inf or non-positive density is
- * found (the totals are still returned). */
+ * momentum[3] = sum (j_A + j_B), with rho and j the moments of Sec. 2 Eq. 6
+ * summed over the box's nodes (the ghost boundary does not conserve them, which
+ * is why Sec. 2 puts mass back into the droplet).  Accumulated in FP64 whatever
+ * the storage format; deterministic fixed-order reduction.  Synchronises the
+ * stream.  EUNSTABLE if a NaN/Inf or non-positive density is found (the totals
+ * are still returned). */
 sclbm_status sclbm_totals(sclbm_ctx *ctx, int32_t box, double mass[2], double momentum[3]);
 
 /* Indicator moments of one box at time n, phi = [rho_A > rho_B], about x_c,
  * written as 10 FP64 values to device memory: S0, S1x, S1y, S1z, S2xx, S2xy,
- * S2xz, S2yy, S2yz, S2zz.  Does not synchronise (for time series: collect many,
- * copy once). */
+ * S2xz, S2yy, S2yz, S2zz.  They give the droplet's inertia tensor, whose
+ * eigenvalues set the ellipsoid semi-axes and the deformation D of Sec. 2
+ * Eq. 4 (sclbm_droplet_from_moments); the paper names the tensor but not how
+ * it is measured, the sharp indicator is this library's choice.  Does not
+ * synchronise (for time series: collect many, copy once).  Errors: EINVAL. */
 sclbm_status sclbm_droplet_moments(sclbm_ctx *ctx, int32_t box, double *dev_out10);
 
 /* The same 10 moments for every box in one pass, dev_out[nbox][10] (device).
@@ -269,6 +305,14 @@ sclbm_status sclbm_default_launch(const sclbm_config *cfg, int32_t *tile_rows, i
  * must cover steps n .. n + trial_steps.  Synchronises. */
 sclbm_status sclbm_autotune(sclbm_ctx *ctx, int32_t trial_steps, int32_t *tile_rows, int32_t *zchunk,
                             int32_t *tile_waves, float *best_ms);
+
+/* Semi-axes over the reference radius of n Maffettone-Minale tensors M[n][9]
+ * (host memory, Sec. 2 Eqs. 1-2: M = I is the sphere, an ellipsoid has the
+ * squared semi-axes as eigenvalues): axes[n][3] = sqrt of the eigenvalues of
+ * the symmetric part of M, descending (closed-form 3x3 eigenvalues, as in
+ * sclbm_droplet_from_moments; a negative eigenvalue from rounding gives 0).
+ * Host only, no GPU work.  Errors: EINVAL (NULL pointer, n < 0). */
+sclbm_status sclbm_mm_semi_axes(const double *M, int64_t n, double *axes);
 
 /* Maffettone-Minale morphology tensor (Sec. 2 Eqs. 1, 2, 5) for ntraj
  * trajectories on the GPU, one thread each, FP64 classical RK4 with `substeps`

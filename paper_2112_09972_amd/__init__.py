@@ -54,7 +54,8 @@ EXPORTS = [
     "sclbm_state_bytes", "sclbm_save", "sclbm_load", "sclbm_set_launch", "sclbm_get_launch", "sclbm_default_launch",
     "sclbm_last_error", "sclbm_step_graph", "sclbm_autotune", "sclbm_droplet_moments_all", "sclbm_mm_integrate",
     "sclbm_droplet_surface_all", "sclbm_deformation_lbm", "sclbm_droplet_mass_all", "sclbm_reinject",
-    "sclbm_droplet_moments_all_static",
+    "sclbm_droplet_moments_all_static", "sclbm_set_gradient", "sclbm_init_uniform", "sclbm_set_health_check",
+    "sclbm_mm_semi_axes",
     # droplet-shape surrogate (sclmlp.h)
     "sclmlp_workspace_bytes", "sclmlp_create", "sclmlp_destroy", "sclmlp_set_params", "sclmlp_get_params",
     "sclmlp_get_grads", "sclmlp_set_normalization", "sclmlp_predict", "sclmlp_gradients", "sclmlp_adam",
@@ -82,6 +83,10 @@ def _load_library():
         "sclbm_init_droplet": [P, I32, dp, D, D, D, D, dp],
         "sclbm_init_fields": [P, I32, P, P, P],
         "sclbm_set_gradient_table": [P, I32, dp, I64, I64],
+        "sclbm_set_gradient": [P, I32, dp],
+        "sclbm_init_uniform": [P, I32, D, D, dp],
+        "sclbm_set_health_check": [P, I64],
+        "sclbm_mm_semi_axes": [dp, I64, dp],
         "sclbm_step": [P, I64],
         "sclbm_step_graph": [P, I64],
         "sclbm_autotune": [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32),
@@ -194,6 +199,29 @@ def sclbm_set_gradient_table(ctx, box, A_rows: np.ndarray, first_step: int):
     a = np.ascontiguousarray(np.asarray(A_rows, dtype=np.float64).reshape(-1, 9))
     _check(_lib.sclbm_set_gradient_table(ctx, box, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                          int(first_step), a.shape[0]))
+
+
+def sclbm_set_gradient(ctx, box, A):
+    _check(_lib.sclbm_set_gradient(ctx, box, _dvec(A, 9)))
+
+
+def sclbm_init_uniform(ctx, box, rho_a, rho_b, u0=None):
+    _check(_lib.sclbm_init_uniform(ctx, box, float(rho_a), float(rho_b), _dvec(u0, 3) if u0 is not None else None))
+
+
+def sclbm_set_health_check(ctx, every: int):
+    _check(_lib.sclbm_set_health_check(ctx, int(every)))
+
+
+def sclbm_mm_semi_axes(M) -> np.ndarray:
+    """Semi-axes over R of Maffettone-Minale tensors M[..., 3, 3], descending: shape [..., 3]."""
+    M = np.asarray(M, dtype=np.float64)
+    assert M.shape[-2:] == (3, 3)
+    m = np.ascontiguousarray(M.reshape(-1, 9))
+    out = np.zeros((m.shape[0], 3))
+    _check(_lib.sclbm_mm_semi_axes(m.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m.shape[0],
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(M.shape[:-2] + (3,))
 
 
 def sclbm_step(ctx, nsteps: int):
@@ -411,6 +439,15 @@ class Lattice:
         self._sync_torch()
         sclbm_init_fields(self.ctx, box, ra.data_ptr(), rb.data_ptr(), uu.data_ptr() if uu is not None else None)
         self.stream.synchronize()
+
+    def init_uniform(self, rho_a, rho_b, u0=None, box=-1):
+        sclbm_init_uniform(self.ctx, box, rho_a, rho_b, u0)
+
+    def set_gradient(self, A, box=-1):
+        sclbm_set_gradient(self.ctx, box, A)
+
+    def set_health_check(self, every):
+        sclbm_set_health_check(self.ctx, every)
 
     def set_gradient_table(self, A_rows, first_step=0, box=0):
         sclbm_set_gradient_table(self.ctx, box, A_rows, first_step)

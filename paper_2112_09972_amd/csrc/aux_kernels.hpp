@@ -44,9 +44,11 @@ __device__ __forceinline__ void node_xyz(const BoxGeom &g, int64_t k, int &x, in
 struct DropletInit {
     double ctr[3], radius, width, rho_in, rho_out;
     Mat3 A0;
+    double u0[3];  // mode 2: uniform velocity (densities rho_in for A, rho_out for B)
 };
 
-// mode 0: tanh droplet (DropletInit); mode 1: FP64 fields rho_a, rho_b, u.
+// mode 0: tanh droplet (DropletInit); mode 1: FP64 fields rho_a, rho_b, u;
+// mode 2: uniform densities (rho_in, rho_out) moving with u0.
 template <int P>
 __global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, __half *ref, BoxGeom g, int mode, DropletInit d,
                                               const double *rho_a, const double *rho_b, const double *u) {
@@ -67,6 +69,12 @@ __global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, __half *re
         ux = A[0] * ex + A[1] * ey + A[2] * ez;
         uy = A[3] * ex + A[4] * ey + A[5] * ez;
         uz = A[6] * ex + A[7] * ey + A[8] * ez;
+    } else if (mode == 2) {
+        ra = d.rho_in;
+        rb = d.rho_out;
+        ux = d.u0[0];
+        uy = d.u0[1];
+        uz = d.u0[2];
     } else {
         ra = rho_a[k];
         rb = rho_b[k];

@@ -163,6 +163,7 @@ struct sclbm_ctx {
     int64_t N;
     BoxGeom geom;
     int device = 0;   // HIP device current at create
+    int64_t health_every = 0;  // check every box for NaN/Inf and non-positive densities every so many steps (0: off)
 
     void *fbuf(int which) { return ws + (which ? lay.f1 : lay.f0); }
     __half *refbuf(int which) {
@@ -415,7 +416,7 @@ sclbm_status reduce_final(sclbm_ctx *c, int nblk, double *host_out) {
 // values of box b0 + i go to c->result() + 16 i (device).
 // Partials [box][block][16] go to `partial` (nb * stats_blocks * 16 doubles) and
 // the final values to `result` (nb * 16); by default the workspace's areas.
-sclbm_status launch_stats(sclbm_ctx *c, int32_t b0, int32_t nb, double *partial = nullptr, double *result = nullptr) {
+sclbm_status launch_stats(sclbm_ctx *c, int32_t b0, int32_t nb, double *partial, double *result) {
     const int bpb = int(stats_blocks(&c->cfg));
     if (!partial) partial = c->partial();
     if (!result) result = c->result();
@@ -609,7 +610,69 @@ sclbm_status sclbm_set_gradient_table(sclbm_ctx *c, int32_t box, const double *A
     return SCLBM_OK;
 }
 
+sclbm_status sclbm_init_uniform(sclbm_ctx *c, int32_t box, double rho_a, double rho_b, const double u0[3]) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, true))) return st;
+    if (!(rho_a > 0.0) || !(rho_b > 0.0)) return fail(SCLBM_EINVAL, "densities must be positive");
+    DropletInit d{};
+    d.rho_in = rho_a;
+    d.rho_out = rho_b;
+    for (int k = 0; k < 3; ++k) {
+        d.u0[k] = u0 ? u0[k] : 0.0;
+        if (!std::isfinite(d.u0[k])) return fail(SCLBM_EINVAL, "non-finite velocity");
+    }
+    return init_common(c, box, 2, d, nullptr, nullptr, nullptr);
+}
+
+sclbm_status sclbm_set_gradient(sclbm_ctx *c, int32_t box, const double A[9]) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if ((st = check_box(c, box, true))) return st;
+    if (!A) return fail(SCLBM_EINVAL, "null gradient");
+    const int64_t n = c->cfg.table_len;
+    std::vector<double> rows;
+    try {
+        rows.resize(size_t(n) * 9);
+    } catch (const std::bad_alloc &) {
+        return fail(SCLBM_EINVAL, "host allocation of %lld rows failed", (long long)n);
+    }
+    for (int64_t t = 0; t < n; ++t)
+        for (int k = 0; k < 9; ++k) rows[size_t(t) * 9 + k] = A[k];
+    const int b0 = box < 0 ? 0 : box, b1 = box < 0 ? c->cfg.nbox : box + 1;
+    for (int b = b0; b < b1; ++b)
+        if ((st = sclbm_set_gradient_table(c, b, rows.data(), c->n, n))) return st;
+    return SCLBM_OK;
+}
+
+sclbm_status sclbm_set_health_check(sclbm_ctx *c, int64_t every) {
+    sclbm_status st = check_ctx(c);
+    if (st) return st;
+    if (every < 0) return fail(SCLBM_EINVAL, "every must be >= 0");
+    c->health_every = every;
+    return SCLBM_OK;
+}
+
 namespace {
+
+sclbm_status launch_stats(sclbm_ctx *c, int32_t b0, int32_t nb, double *partial, double *result);
+
+// Every box's FP64 totals and count of nodes with a NaN/Inf or non-positive
+// density at the current time (synchronises); EUNSTABLE names the first bad box.
+sclbm_status health_check(sclbm_ctx *c) {
+    sclbm_status st = launch_stats(c, 0, c->cfg.nbox, nullptr, nullptr);
+    if (st) return st;
+    std::vector<double> r(size_t(c->cfg.nbox) * NSTAT);
+    HIP_TRY(hipMemcpyAsync(r.data(), c->result(), r.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int b = 0; b < c->cfg.nbox; ++b) {
+        const double *v = r.data() + size_t(b) * NSTAT;
+        if (v[15] != 0.0 || !std::isfinite(v[0]) || !std::isfinite(v[1]))
+            return fail(SCLBM_EUNSTABLE, "box %d at step %lld: %.0f nodes with NaN/Inf or non-positive density", b,
+                        (long long)c->n, v[15]);
+    }
+    return SCLBM_OK;
+}
 
 sclbm_status check_table(sclbm_ctx *c, int64_t nsteps) {
     if (c->cfg.bc != SCLBM_BC_GHOST) return SCLBM_OK;
@@ -684,10 +747,19 @@ sclbm_status sclbm_step(sclbm_ctx *c, int64_t nsteps) {
     if (nsteps < 0) return fail(SCLBM_EINVAL, "nsteps < 0");
     if (nsteps == 0) return SCLBM_OK;
     if ((st = check_table(c, nsteps))) return st;
-    hipError_t e = enqueue_steps(c, nsteps, c->par);
-    if (e != hipSuccess) return fail(SCLBM_EHIP, "step kernel: %s", hipGetErrorString(e));
-    c->par ^= int(nsteps & 1);
-    c->n += nsteps;
+    // with the health check on, steps go in segments that end where the time is a
+    // multiple of health_every, and each such time is checked
+    int64_t left = nsteps;
+    while (left > 0) {
+        int64_t seg = left;
+        if (c->health_every > 0) seg = std::min(left, c->health_every - c->n % c->health_every);
+        hipError_t e = enqueue_steps(c, seg, c->par);
+        if (e != hipSuccess) return fail(SCLBM_EHIP, "step kernel: %s", hipGetErrorString(e));
+        c->par ^= int(seg & 1);
+        c->n += seg;
+        left -= seg;
+        if (c->health_every > 0 && c->n % c->health_every == 0 && (st = health_check(c))) return st;
+    }
     return SCLBM_OK;
 }
 
@@ -721,6 +793,7 @@ sclbm_status sclbm_step_graph(sclbm_ctx *c, int64_t nsteps) {
     }
     HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
     c->n += nsteps;  // even: the parity is unchanged
+    if (c->health_every > 0) return health_check(c);  // once, after the replay
     return SCLBM_OK;
 }
 
@@ -826,7 +899,7 @@ sclbm_status sclbm_totals(sclbm_ctx *c, int32_t box, double mass[2], double mome
     if (st) return st;
     if ((st = check_box(c, box, false))) return st;
     if (!mass || !momentum) return fail(SCLBM_EINVAL, "null output");
-    if ((st = launch_stats(c, box, 1))) return st;
+    if ((st = launch_stats(c, box, 1, nullptr, nullptr))) return st;
     double r[NSTAT];
     HIP_TRY(hipMemcpyAsync(r, c->result(), sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -844,7 +917,7 @@ sclbm_status sclbm_droplet_moments(sclbm_ctx *c, int32_t box, double *dev_out10)
     if (st) return st;
     if ((st = check_box(c, box, false))) return st;
     if (!dev_out10) return fail(SCLBM_EINVAL, "null output");
-    if ((st = launch_stats(c, box, 1))) return st;
+    if ((st = launch_stats(c, box, 1, nullptr, nullptr))) return st;
     HIP_TRY(hipMemcpyAsync(dev_out10, c->result() + 5, 10 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     return SCLBM_OK;
 }
@@ -853,7 +926,7 @@ sclbm_status sclbm_droplet_moments_all(sclbm_ctx *c, double *dev_out) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
     if (!dev_out) return fail(SCLBM_EINVAL, "null output");
-    if ((st = launch_stats(c, 0, c->cfg.nbox))) return st;
+    if ((st = launch_stats(c, 0, c->cfg.nbox, nullptr, nullptr))) return st;
     HIP_TRY(hipMemcpy2DAsync(dev_out, 10 * sizeof(double), c->result() + 5, NSTAT * sizeof(double), 10 * sizeof(double),
                              size_t(c->cfg.nbox), hipMemcpyDeviceToDevice, c->stream));
     return SCLBM_OK;
@@ -907,12 +980,28 @@ sclbm_status sclbm_droplet_from_moments(const double mom[10], const double cente
     return SCLBM_OK;
 }
 
+sclbm_status sclbm_mm_semi_axes(const double *M, int64_t n, double *axes) {
+    if (!M || !axes) return fail(SCLBM_EINVAL, "null argument");
+    if (n < 0) return fail(SCLBM_EINVAL, "n must be >= 0");
+    for (int64_t t = 0; t < n; ++t) {
+        const double *m = M + 9 * t;
+        // symmetric part (the integrator keeps M symmetric up to rounding)
+        const double c00 = m[0], c11 = m[4], c22 = m[8];
+        const double c01 = 0.5 * (m[1] + m[3]), c02 = 0.5 * (m[2] + m[6]), c12 = 0.5 * (m[5] + m[7]);
+        const double sm[6] = {c00, c01, c02, c11, c12, c22};
+        double lam[3];
+        sym3_eigenvalues(sm, lam);
+        for (int k = 0; k < 3; ++k) axes[3 * t + k] = std::sqrt(std::max(0.0, lam[k]));
+    }
+    return SCLBM_OK;
+}
+
 sclbm_status sclbm_droplet(sclbm_ctx *c, int32_t box, sclbm_droplet_stats *out) {
     sclbm_status st = check_ctx(c);
     if (st) return st;
     if ((st = check_box(c, box, false))) return st;
     if (!out) return fail(SCLBM_EINVAL, "null output");
-    if ((st = launch_stats(c, box, 1))) return st;
+    if ((st = launch_stats(c, box, 1, nullptr, nullptr))) return st;
     double r[NSTAT];
     HIP_TRY(hipMemcpyAsync(r, c->result(), sizeof r, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import Lattice, mm_integrate, sclbm_droplet_from_moments
+from . import Lattice, mm_integrate, sclbm_droplet_from_moments, sclbm_mm_semi_axes
 from . import workloads as wl
 from .mlp import NIN, Network, init_params
 
@@ -295,8 +295,7 @@ def mm_shapes(run: EnsembleRun, tau: float = wl.TAU, chi: float = 1.0, device="c
     tau_d = wl.eta_s(tau) * run.radius / wl.SIGMA
     A = np.stack(run.tables)                                   # (nbox, steps + 1, 9)
     M = mm_integrate(A, tau_d, chi=chi, substeps=1, record_every=run.stride, device=device).cpu().numpy()
-    lam = np.linalg.eigvalsh(0.5 * (M + np.swapaxes(M, -1, -2)))[..., ::-1]
-    return np.sqrt(np.clip(lam, 0.0, None))
+    return sclbm_mm_semi_axes(M)
 
 
 def errors(pred: np.ndarray, truth: np.ndarray) -> dict:

@@ -139,3 +139,26 @@ def test_default_launch_rejects_invalid_config():
     with pytest.raises(sc.SclbmError) as ei:
         sc.sclbm_default_launch(cfg(nx=2))
     assert ei.value.status == sc.SCLBM_EINVAL
+
+
+def test_mm_semi_axes_host_call():
+    """sclbm_mm_semi_axes (host only): square roots of the eigenvalues of the
+    symmetric part, descending, against numpy's symmetric eigen-solver on
+    ellipsoids R diag(a^2) R^T with random rotations, plus the sphere and a
+    repeated axis (the trigonometric solution's degenerate branches)."""
+    import paper_2112_09972_amd as sc
+    rng = np.random.default_rng(7)
+    Ms = []
+    for _ in range(200):
+        q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        a = np.sort(rng.uniform(0.3, 3.0, 3))[::-1]
+        M = q @ np.diag(a * a) @ q.T
+        M += 1e-14 * rng.standard_normal((3, 3))  # not exactly symmetric, as an integrator leaves it
+        Ms.append(M)
+    Ms.append(np.eye(3))
+    Ms.append(np.diag([2.0, 0.5, 0.5]))
+    Ms = np.array(Ms)
+    got = sc.sclbm_mm_semi_axes(Ms.reshape(2, -1, 3, 3)).reshape(-1, 3)
+    ref = np.sqrt(np.linalg.eigvalsh(0.5 * (Ms + Ms.transpose(0, 2, 1)))[:, ::-1])
+    assert np.allclose(got, ref, rtol=1e-10, atol=1e-12)
+    assert np.all(np.diff(got, axis=1) <= 0)
