@@ -226,19 +226,24 @@ def test_laplace_law(calibration):
 
 def test_ghost_boundary_relaxes_to_linear_flow():
     """Single phase (G = 0), fluid at rest, simple shear imposed only through the
-    ghost nodes: E0 falls below 0.1 once the flow has developed (Sec. 4 Eq. 16)."""
-    L = 16
-    gamma = 0.05 / (L / 2)
+    ghost nodes of a box of the paper's validation size L_s = 48 at tau = 1 with
+    the velocity scale u_LBM = L_s ||G||_inf = 0.1 (Table 1, Sec. 4 Eq. 15): the
+    global error E0 of Sec. 4 Eq. 16 falls below the paper's acceptance level 0.1
+    within 500 steps and keeps falling (below 0.01 at 1000 steps; the linear
+    profile with equilibrium ghosts is a steady state of the scheme)."""
+    L = 48
+    gamma = 0.1 / L
     A = np.zeros(9)
     A[2] = gamma
     o = oracle.Oracle(L, L, L, periodic=False, tau=(1.0, 1.0), g=0.0, rho_b=(0.5, 0.5))
     o.init_fields(np.full(o.shape, 0.5), np.full(o.shape, 0.5))
-    errs = []
-    for _ in range(6):
+    errs = [oracle.velocity_error(o.fields()[2], A, o.xc)]
+    for _ in range(2):
         o.run(500, np.tile(A, (500, 1)))
         errs.append(oracle.velocity_error(o.fields()[2], A, o.xc))
-    assert errs[0] > errs[-1]
-    assert errs[-1] < 0.1
+    assert errs[0] > 0.99  # at rest: E0 = 1
+    assert errs[1] < 0.1
+    assert errs[2] < 0.01
     # a wrong-signed boundary would drive the opposite flow: E0 near 2
     assert oracle.velocity_error(-o.fields()[2], A, o.xc) > 1.5
 
@@ -250,34 +255,44 @@ def far_field(calibration, R):
 
 
 def test_taylor_deformation(calibration):
-    """Steady simple shear at viscosity ratio 1: D = (35/32) Ca for an unbounded
-    droplet, raised by the confinement of the driven boundary.  The closed form
-    of Shapira and Haber for a droplet midway between two plates a distance h from
-    its centre, D = (35/32) Ca [1 + C_s (1 + 5 chi / 2)/(1 + chi) (R/h)^3] with
-    C_s = 5.6996, is the pin; 15 % tolerance."""
+    """Steady simple shear at viscosity ratio 1, Ca = 0.025, 0.05, 0.1: D = (35/32) Ca
+    for an unbounded droplet, raised by the confinement of the driven boundary.
+    The closed form of Shapira and Haber for a droplet midway between two plates a
+    distance h from its centre, D = (35/32) Ca [1 + C_s (1 + 5 chi / 2)/(1 + chi)
+    (R/h)^3] with C_s = 5.6996, is first order in Ca: the slope of D against Ca
+    over the two smaller Ca (least squares through the origin) matches it within
+    10 %, every Ca within 20 %, and at Ca = 0.1 D lies above the linear law (the
+    second-order growth of the deformation)."""
     G = calibration["g_ab"]
     sigma = calibration["sigma"]
-    L, R, Ca = 48, 8.0, 0.05
+    L, R = 48, 8.0
     eta = 1.04 * (1.0 - 0.5) / 3.0
-    gamma = Ca * sigma / (eta * R)
-    A = np.zeros(9)
-    A[2] = gamma
-    o = oracle.Oracle(L, L, L, periodic=False, tau=(1.0, 1.0), g=G, rho_b=far_field(calibration, R))
-    o.init_droplet(o.xc, R, 2.0, 1.0, 0.04, A)
-    Ds = []
-    for _ in range(2):
-        o.run(500, np.tile(A, (500, 1)))
-        ra, rb, _ = o.fields()
-        st = oracle.droplet_stats(ra, rb, o.xc)
-        Ds.append(st["deformation"])
-    D = Ds[-1]
-    assert abs(Ds[-1] - Ds[-2]) < 0.05 * D  # steady
-    h = L / 2.0
-    chi = 1.0
-    D_pred = 35.0 / 32.0 * Ca * (1.0 + 5.6996 * (1 + 2.5 * chi) / (1 + chi) * (st["r_eq"] / h) ** 3)
-    assert abs(D / D_pred - 1.0) < 0.15
-    # and well above the unbounded value for this confined box
-    assert D > 35.0 / 32.0 * Ca
+    h, chi = L / 2.0, 1.0
+    cas, Ds, preds = (0.025, 0.05, 0.1), [], []
+    for Ca in cas:
+        gamma = Ca * sigma / (eta * R)
+        A = np.zeros(9)
+        A[2] = gamma
+        o = oracle.Oracle(L, L, L, periodic=False, tau=(1.0, 1.0), g=G, rho_b=far_field(calibration, R))
+        o.init_droplet(o.xc, R, 2.0, 1.0, 0.04, A)
+        D = []
+        for steps in (750, 250):
+            o.run(steps, np.tile(A, (steps, 1)))
+            ra, rb, _ = o.fields()
+            st = oracle.droplet_stats(ra, rb, o.xc)
+            D.append(st["deformation"])
+        assert abs(D[1] - D[0]) < 0.05 * D[1], (Ca, D)  # steady
+        Ds.append(D[1])
+        preds.append(35.0 / 32.0 * Ca * (1.0 + 5.6996 * (1 + 2.5 * chi) / (1 + chi) * (st["r_eq"] / h) ** 3))
+    cas, Ds, preds = np.array(cas), np.array(Ds), np.array(preds)
+    slope = np.dot(cas[:2], Ds[:2]) / np.dot(cas[:2], cas[:2])
+    slope_pred = np.mean(preds[:2] / cas[:2])
+    print("D", Ds, "D/Ca", Ds / cas, "slope %.4f against %.4f" % (slope, slope_pred))
+    assert abs(slope / slope_pred - 1.0) < 0.10
+    assert np.all(np.abs(Ds / preds - 1.0) < 0.20)
+    assert Ds[2] > slope * cas[2]
+    # well above the unbounded value for this confined box
+    assert np.all(Ds > 35.0 / 32.0 * cas)
 
 
 @pytest.mark.parametrize("axes,rot", [((10.0, 8.0, 6.0), False), ((9.0, 7.0, 5.0), True)])
