@@ -66,26 +66,47 @@ def measured_traffic(workload: str):
     return int(d["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(case, seconds: float = 15.0):
-    """The FP64 oracle on the same box and drive, timed on the host cores."""
+def cpu_baseline(case):
+    """The FP64 oracle (plain C, OpenMP over z) timed on the host cores: the 32^3
+    shear box, one 64^3 ensemble box and the benchmark's 128^3 box with their own
+    drives, on one core and on all cores (the 128^3 box only on all: one step
+    there takes seconds on one core).  Each case: one warm-up step, then the median
+    MLUPS of 5 repetitions of k steps, k chosen from the warm-up so that a
+    repetition takes about 0.3 s.  `value` is the 128^3 box on all cores."""
     import oracle
-    o = oracle.Oracle(case.n, case.n, case.n, periodic=False, tau=(case.tau, case.tau), g=wl.G_AB,
-                      rho_b=case.rho_b)
-    tab = case.tables[0]
-    o.init_droplet(o.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
-    o.step(tab[0])  # warm-up (page-in, thread start)
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        o.step(tab[1 + steps])
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or steps >= 200:
-            break
-    return {"value": round(case.n ** 3 * steps / el / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d lattice steps of the %d^3 FP64 droplet box (steps 1..%d of the same OU drive), %.1f s"
-                      % (steps, case.n, steps, el)}
+    all_threads = oracle.num_threads()
+    c1, c4 = wl.case_c1(), wl.case_c4(nsteps=400, nbox=1)
+    boxes = [(c1, (1, all_threads)), (c4, (1, all_threads)), (case, (all_threads,))]
+    cases = []
+    t_start = time.perf_counter()
+    for cs, thread_counts in boxes:
+        tab = cs.tables[0]
+        for th in thread_counts:
+            oracle.set_num_threads(th)
+            o = oracle.Oracle(cs.n, cs.n, cs.n, periodic=False, tau=(cs.tau, cs.tau), g=wl.G_AB, rho_b=cs.rho_b)
+            o.init_droplet(o.xc, cs.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
+            t0 = time.perf_counter()
+            o.step(tab[0])  # warm-up (page-in, thread start)
+            k = max(1, int(round(0.3 / (time.perf_counter() - t0))))
+            rates = []
+            step = 1
+            for _ in range(5):
+                t0 = time.perf_counter()
+                for _ in range(k):
+                    o.step(tab[step])
+                    step += 1
+                rates.append(cs.n ** 3 * k / (time.perf_counter() - t0) / 1e6)
+            med = float(np.median(rates))
+            cases.append({"box": cs.n, "workload": cs.name, "threads": th, "steps_per_rep": k, "reps": 5,
+                          "mlups": round(med, 3), "mlups_per_core": round(med / th, 3)})
+            del o
+    oracle.set_num_threads(all_threads)
+    big = cases[-1]
+    return {"value": big["mlups"], "unit": "MLUPS", "cores": big["threads"], "kind": "oracle",
+            "sample": "FP64 oracle on the %d^3 droplet box (same OU drive), median of 5 repetitions of %d steps on "
+                      "%d threads; 32^3 and 64^3 boxes on 1 and %d threads in `cases`; %.1f s in all"
+                      % (case.n, big["steps_per_rep"], big["threads"], all_threads, time.perf_counter() - t_start),
+            "host_cpus": os.cpu_count(), "cases": cases}
 
 
 def precision_study(sc, nsteps: int):
@@ -195,7 +216,6 @@ def main():
     ap.add_argument("--steps", type=int, default=400, help="timed samples of 50 lattice steps")
     ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--launch", type=str, default="", help="tile_rows,zchunk[,tile_waves]")
     ap.add_argument("--workload", choices=["c2", "c3"], default="c2",
                     help="c2: the headline 128^3 FP32 box (default); c3: the 256^3 precision study")
@@ -320,7 +340,7 @@ def main():
     del lat, moments
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(case)
         log("cpu baseline: %s" % out["cpu_baseline"]["value"])
     if not args.no_surrogate:
         out["surrogate"] = surrogate_study(args.surrogate_train_steps, log=log)

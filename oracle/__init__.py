@@ -77,6 +77,7 @@ def _load():
         lib.orc_stencil.argtypes = [ip, dp]
         lib.orc_equilibrium.argtypes = [D, dp, dp]
         lib.orc_num_threads.restype = I
+        lib.orc_set_num_threads.argtypes = [I]
         _lib = lib
     return _lib
 
@@ -98,6 +99,11 @@ def stencil():
 def num_threads() -> int:
     """OpenMP threads the oracle's loops run on."""
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's following loops (n >= 1)."""
+    _load().orc_set_num_threads(int(n))
 
 
 def equilibrium(rho: float, u) -> np.ndarray:

@@ -119,6 +119,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Set the threads of the following OpenMP loops (timing on 1 core and on all). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 void orc_stencil(int *c_out /* [Q][3] */, double *w_out /* [Q] */) {
     orc_stencil_init();
     for (int i = 0; i < Q; i++) {
