@@ -109,6 +109,42 @@ def cpu_baseline(case):
             "host_cpus": os.cpu_count(), "cases": cases}
 
 
+def c1_against_oracle(sc, nsteps: int = 1000):
+    """The 32^3 droplet box in steady simple shear at Ca = 0.1 (tau = 1) in every
+    storage format against the FP64 oracle after `nsteps` steps: the largest
+    per-node relative density error, the mass drift per component and the
+    deformation D of the sheared droplet (Sec. 2 Eq. 4) next to the oracle's."""
+    import oracle
+    case = wl.case_c1()
+    tab = case.tables[0][:nsteps]
+    rho_b = case.rho_b
+    o = oracle.Oracle(case.n, case.n, case.n, periodic=False, tau=(case.tau, case.tau), g=wl.G_AB, rho_b=rho_b)
+    o.init_droplet(o.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
+    om0, _ = o.totals()
+    o.run(nsteps, tab)
+    om, _ = o.totals()
+    oa, ob, _ = o.fields()
+    od = oracle.droplet_stats(oa, ob, o.xc)["deformation"]
+    out = {"workload": case.name, "lattice_steps": nsteps, "oracle": {"mass_drift_rel": [float(v) for v in (om - om0) / om0],
+                                                                      "deformation": float(od)}, "results": {}}
+    for prec in ("f64", "f32", "f32d", "f16dev", "bf16dev"):
+        lat = sc.Lattice(case.n, case.n, case.n, bc="ghost", prec=prec, table_len=nsteps, g_ab=wl.G_AB, rho_b=rho_b,
+                         mach_max=0.25)
+        lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, tab[0])
+        lat.set_gradient_table(tab, 0)
+        m0, _ = lat.totals()
+        lat.step(nsteps)
+        m1, _ = lat.totals(check=False)
+        ra, rb = (t.cpu().numpy() for t in lat.fields(velocity=False))
+        err = max(float(np.max(np.abs(ra - oa) / oa)), float(np.max(np.abs(rb - ob) / ob)))
+        d = lat.droplet()["deformation"]
+        out["results"][prec] = {"max_rel_density_err": err, "mass_drift_rel": [float(v) for v in (m1 - m0) / m0],
+                                "deformation": float(d), "deformation_abs_err": float(abs(d - od))}
+        lat.close()
+    print(json.dumps({"c1_against_oracle": out}), flush=True)
+    return out
+
+
 def precision_study(sc, nsteps: int):
     """The 256^3 droplet box (R = 32, OU drive seed 3) in every storage format:
     MLUPS, algorithmic bytes per update, mass drift and semi-axis / deformation
@@ -156,6 +192,7 @@ def precision_study(sc, nsteps: int):
         torch.cuda.empty_cache()
     a64, d64 = series["f64"]
     out["f64_deformation_range"] = [float(d64.min()), float(d64.max())]
+    out["c1_against_oracle"] = c1_against_oracle(sc)
     print(json.dumps(out))
 
 

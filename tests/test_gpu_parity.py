@@ -291,10 +291,11 @@ def test_context_starts_at_default_launch(sc, nxyz, prec):
 
 def test_full_size_128_fp32_all_nodes(sc):
     """The 128^3 FP32 box at the benchmark's launch shape against the oracle on
-    every node after 6 steps of the OU drive."""
+    every node after 60 steps of the OU drive (the oracle's 1.3e8 node updates
+    take a few seconds on the host cores)."""
     case = wl.case_c2(nsteps=200)
     tab = case.tables[0]
-    steps = 6
+    steps = 60
     lat, o = make_pair(sc, 128, prec="f32", R=case.radius, A=tab[0], steps=steps, mach_max=wl.MACH_MAX)
     lat.set_gradient_table(tab[:steps], 0)
     lat.step(steps)
@@ -322,6 +323,7 @@ def test_c1_deviation_formats_500_steps(sc, prec):
         l.set_gradient_table(tab, 0)
     m0, _ = lat.totals()
     m064, _ = ref64.totals()
+    o_mass0, _ = o.totals()
     lat.step(steps)
     ref64.step(steps)
     o.run(steps, tab)
@@ -335,6 +337,17 @@ def test_c1_deviation_formats_500_steps(sc, prec):
     a = lat.droplet()["semi_axes"]
     a64 = ref64.droplet()["semi_axes"]
     assert np.all(np.abs(a - a64) / a64 <= 2 * DEV_TOL[prec])
+    # against the FP64 oracle itself: mass drift per component and the deformation
+    # D (Sec. 2 Eq. 4) of the sheared droplet
+    om, _ = o.totals()
+    om0 = o_mass0
+    drift, odrift = (m - m0) / m0, (om - om0) / om0
+    oa, ob, _ = o.fields()
+    d_or = oracle.droplet_stats(oa, ob, o.xc)["deformation"]
+    d = lat.droplet()["deformation"]
+    print("%s: mass drift %s (oracle %s), D %.5f (oracle %.5f)" % (prec, drift, odrift, d, d_or))
+    assert np.all(np.abs(drift - odrift) <= DEV_TOL[prec])
+    assert abs(d - d_or) <= 2 * DEV_TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
