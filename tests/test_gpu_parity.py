@@ -215,6 +215,36 @@ def test_launch_shape_bits_every_format(sc, prec, bc, nx):
     assert all(np.array_equal(out[0][64:], o[64:]) for o in out[1:])
 
 
+@pytest.mark.parametrize("bc", ["ghost", "periodic"])
+@pytest.mark.parametrize("nxyz,shapes", [((128, 10, 9), [(4, 3, 2), (4, 4, 1)]), ((64, 13, 11), [(8, 5, 1), (4, 3, 2)]),
+                                         ((192, 9, 7), [(4, 3, 2), (4, 3, 1)])])
+def test_fp32_whole_row_tiles(sc, bc, nxyz, shapes):
+    """FP32 on tiles that hold whole rows of a multiple of 64 nodes (128 x 4 tiles
+    on nx = 128, 64 x 8 on nx = 64; the ring columns at the x faces then wrap
+    inside the tile) against the oracle, and bit for bit against tiles that split
+    the rows (64-wide tiles on nx = 128, 128-wide on nx = 192) or another whole-row
+    tile (nx = 64)."""
+    A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
+    steps = 30
+    tab = np.tile(A, (steps, 1))
+    out = []
+    for shape in shapes:
+        lat, o = make_pair(sc, None, nxyz=nxyz, prec="f32", bc=bc, R=4.0, A=A if bc == "ghost" else None,
+                           steps=steps)
+        lat.set_launch(*shape)
+        if bc == "ghost":
+            lat.set_gradient_table(tab, 0)
+        lat.step(steps)
+        out.append(lat.save())
+        if shape == shapes[0]:
+            o.run(steps, tab if bc == "ghost" else None)
+            err = rel_density_error(lat, o)
+            print("f32 %s %s %s: max rel density error %.3e" % (bc, nxyz, shape, err))
+            assert err <= TOL["f32"]
+        lat.close()
+    assert np.array_equal(out[0][64:], out[1][64:])
+
+
 def test_periodic_conservation_fp64(sc):
     n = 48
     lat, _ = make_pair(sc, n, bc="periodic", R=10.0)
