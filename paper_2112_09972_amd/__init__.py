@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsclbm.so")
+# SCLBM_LIBRARY selects another build of the library (the debug variant
+# libsclbm_debug.so); by default the one next to this file.
+LIB_PATH = os.environ.get("SCLBM_LIBRARY") or os.path.join(_PKG, "libsclbm.so")
 
 SCLBM_OK, SCLBM_EINVAL, SCLBM_ESIZE, SCLBM_EHIP, SCLBM_EUNSTABLE, SCLBM_ESTATE = 0, -1, -2, -3, -4, -5
 BC = {"periodic": 0, "ghost": 1}
@@ -435,7 +437,7 @@ class Lattice:
             u = np.asarray(u, dtype=np.float64)
             if u.shape == (3,):
                 u = u.reshape(3, 1, 1, 1)
-            uu = t.as_tensor(np.ascontiguousarray(np.broadcast_to(u, (3,) + self.shape))).to(self.device)
+            uu = t.as_tensor(np.array(np.broadcast_to(u, (3,) + self.shape), dtype=np.float64)).to(self.device)
         self._sync_torch()
         sclbm_init_fields(self.ctx, box, ra.data_ptr(), rb.data_ptr(), uu.data_ptr() if uu is not None else None)
         self.stream.synchronize()

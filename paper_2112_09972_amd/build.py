@@ -36,19 +36,26 @@ def hipcc() -> str:
     return exe
 
 
-def build_library(verbose: bool = False) -> str:
-    """Compile the library (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I" + os.path.join(ROOT, "include"), "-o", tmp] + SRCS
+DEBUG_LIB = os.path.join(PKG, "libsclbm_debug.so")
+
+
+def build_library(verbose: bool = False, debug: bool = False) -> str:
+    """Compile the library (always recompiles).  debug=True builds
+    libsclbm_debug.so, whose step kernels fill the LDS cells they are about to
+    write with NaN at every plane (reads of unwritten cells become visible)."""
+    lib = DEBUG_LIB if debug else LIB
+    tmp = lib + ".tmp%d" % os.getpid()
+    extra = ["-DSCLBM_DEBUG_FILL=1"] if debug else []
+    cmd = [hipcc()] + HIPCC_FLAGS + extra + ["-I" + os.path.join(ROOT, "include"), "-o", tmp] + SRCS
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l and l.strip())
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + res.stdout)
     if verbose and out:
         print(out)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build_library(verbose="-v" in sys.argv))
+    print(build_library(verbose="-v" in sys.argv, debug="--debug" in sys.argv))

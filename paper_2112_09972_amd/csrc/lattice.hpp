@@ -13,7 +13,30 @@
 
 #include "sclbm.h"
 
+// Debug build (SCLBM_DEBUG_FILL=1, the library's debug variant): the step kernels
+// overwrite the LDS slots they are about to fill with NaN at every plane, so that
+// a read of a cell no thread wrote for that plane turns into NaN populations.
+#ifndef SCLBM_DEBUG_FILL
+#define SCLBM_DEBUG_FILL 0
+#endif
+
 namespace sclbm {
+
+constexpr bool kDebugFill = SCLBM_DEBUG_FILL != 0;
+
+// Quiet-NaN bit patterns of the stored formats (debug fill).
+template <typename T>
+__device__ __forceinline__ T nan_bits(int prec) {
+    if constexpr (sizeof(T) == 8) return T(0x7ff8000000000000ull);
+    if constexpr (sizeof(T) == 2) return T(prec == SCLBM_BF16DEV ? 0x7fc0u : 0x7e00u);
+    return T(prec == SCLBM_BF16DEV ? 0x7fc0u : (prec == SCLBM_F16DEV ? 0x7e00u : 0x7fc00000u));
+}
+
+// Fill n elements of an LDS array with `v`, all threads of the workgroup taking part.
+template <typename T>
+__device__ __forceinline__ void lds_fill(T *p, int n, T v, int tid, int nthreads) {
+    for (int i = tid; i < n; i += nthreads) p[i] = v;
+}
 
 constexpr int Q = 19;
 

@@ -302,6 +302,13 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     for (int k = 0; k < nplanes; ++k) {
         const int z = zfirst + dir * k;
         const int slot = k & 3;
+        if constexpr (kDebugFill) {
+            // debug build: this plane's density slot and the exchange buffer start as NaN
+            __syncthreads();
+            lds_fill(&lds[slot][0][0][0], 2 * (TY + 2) * LW, D(__builtin_nan("")), tid, 64 * WX * TY);
+            lds_fill(&xq[0][0][0][0], 2 * NXD * TY * LW, nan_bits<B>(P), tid, 64 * WX * TY);
+            __syncthreads();
+        }
         // ---- 1. densities of plane z: own node (into the register window) and one
         // ring node per thread ----
         bool own_in;

@@ -155,6 +155,13 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
     for (int k = 0; k < nplanes; ++k) {
         const int z = zfirst + dir * k;
         const int slot = k & 3;
+        if constexpr (kDebugFill) {
+            // debug build: this plane's density slot and the exchange buffer start as NaN
+            __syncthreads();
+            lds_fill(&lds[slot][0][0][0], 2 * (TY + 2) * LW, R(__builtin_nanf("")), tid, 64 * WX * TY);
+            lds_fill(&xq[0][0][0][0], 2 * Q * TY * LW, nan_bits<unsigned short>(P), tid, 64 * WX * TY);
+            __syncthreads();
+        }
         // ---- 1. densities of plane z: the lane's pair and the ring around the tile ----
         const bool own_in = nx_in;
         if (own_in) {
