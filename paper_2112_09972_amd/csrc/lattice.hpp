@@ -204,6 +204,10 @@ struct Prec<SCLBM_F16DEV> {
     static __device__ __forceinline__ B enc(R v, R wref) {
         return __builtin_bit_cast(unsigned short, __float2half_rn(rel_dev(v, wref)));
     }
+    // the same deviation from a precomputed scale s = 1 / wref: v s - 1, one rounding
+    static __device__ __forceinline__ B enc_s(R v, R s) {
+        return __builtin_bit_cast(unsigned short, __float2half_rn(__builtin_fmaf(v, s, -1.0f)));
+    }
     static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
         __builtin_amdgcn_raw_buffer_store_b16((unsigned short)b, r, vo, so, kStoreNT);
     }
@@ -236,6 +240,9 @@ struct Prec<SCLBM_BF16DEV> {
     static __device__ __forceinline__ B enc(R v, R wref) {
         return __builtin_bit_cast(unsigned short, __float2bfloat16(rel_dev(v, wref)));
     }
+    static __device__ __forceinline__ B enc_s(R v, R s) {
+        return __builtin_bit_cast(unsigned short, __float2bfloat16(__builtin_fmaf(v, s, -1.0f)));
+    }
     static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
         __builtin_amdgcn_raw_buffer_store_b16((unsigned short)b, r, vo, so, kStoreNT);
     }
@@ -249,6 +256,16 @@ struct Prec<SCLBM_BF16DEV> {
 __device__ __forceinline__ float ref_load(const __half *p) { return __half2float(*p); }
 __device__ __forceinline__ float ref_round(float v) { return __half2float(__float2half_rn(v)); }
 __device__ __forceinline__ void ref_store(__half *p, float v) { *p = __float2half_rn(v); }
+// Reciprocal of a node's reference density as the step kernels encode against it:
+// computed once per node and plane and kept in LDS beside the density, so that the
+// encoding of a population pushed into the node is one multiply-add (the same
+// function everywhere, so a node's value does not depend on which tile computed it).
+__device__ __forceinline__ float ref_rcp(float rho) { return __builtin_amdgcn_rcpf(ref_round(rho)); }
+// 1 / w_i, exact: 3, 18, 36
+template <typename R>
+__host__ __device__ constexpr R inv_w_of(int i) {
+    return i == 0 ? R(3) : (i < 7 ? R(18) : R(36));
+}
 
 inline bool is_dev(int prec) { return prec == SCLBM_F16DEV || prec == SCLBM_BF16DEV; }
 

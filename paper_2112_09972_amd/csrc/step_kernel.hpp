@@ -181,7 +181,12 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     // that nothing waits for them during the collision) are loaded while the
     // current one collides.  FP64 windows leave no registers for a third plane.
     constexpr bool PREFETCH = sizeof(S) < 8;
-    __shared__ D lds[4][2][TY + 2][LW];
+    // density window: the planes zc - 1, zc, zc + 1 of the collision (slots of the
+    // march); FP32/FP64 keep a fourth slot, the deviation formats use that room for
+    // the reciprocal reference densities of the same planes (rq)
+    constexpr int NSLOT = Prec<P>::DEV ? 3 : 4;
+    __shared__ D lds[NSLOT][2][TY + 2][LW];
+    __shared__ float rq[Prec<P>::DEV ? NSLOT : 1][2][Prec<P>::DEV ? TY + 2 : 1][Prec<P>::DEV ? LW : 1];
     // x exchange: post-collision values with c_x != 0, by component, slot, row and
     // column lx + 1; columns 0 and tw + 1 hold what streams in across the tile's
     // left and right edges (ghost populations, or the periodic wrap)
@@ -301,11 +306,12 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     W fprev[2][Q], fcur[2][Q];
     for (int k = 0; k < nplanes; ++k) {
         const int z = zfirst + dir * k;
-        const int slot = k & 3;
+        const int slot = k % NSLOT;
         if constexpr (kDebugFill) {
             // debug build: this plane's density slot and the exchange buffer start as NaN
             __syncthreads();
             lds_fill(&lds[slot][0][0][0], 2 * (TY + 2) * LW, D(__builtin_nan("")), tid, 64 * WX * TY);
+            if (Prec<P>::DEV) lds_fill(&rq[slot][0][0][0], 2 * (TY + 2) * LW, __builtin_nanf(""), tid, 64 * WX * TY);
             lds_fill(&xq[0][0][0][0], 2 * NXD * TY * LW, nan_bits<B>(P), tid, 64 * WX * TY);
             __syncthreads();
         }
@@ -368,6 +374,10 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             const D r1 = own_in ? pair_density<D>(fcur[1]) : rhobd[1];
             lds[slot][0][ly + 1][lx + 1] = r0;
             lds[slot][1][ly + 1][lx + 1] = r1;
+            if constexpr (DEV) {
+                rq[slot][0][ly + 1][lx + 1] = ref_rcp(float(r0));
+                rq[slot][1][ly + 1][lx + 1] = ref_rcp(float(r1));
+            }
         }
         if (ring_on) {
             D rr[2] = {rhobd[0], rhobd[1]};
@@ -384,6 +394,10 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             }
             lds[slot][0][rsy][rsx] = rr[0];
             lds[slot][1][rsy][rsx] = rr[1];
+            if constexpr (DEV) {
+                rq[slot][0][rsy][rsx] = ref_rcp(float(rr[0]));
+                rq[slot][1][rsy][rsx] = ref_rcp(float(rr[1]));
+            }
         }
         __syncthreads();
         // ---- 2. the next plane's loads go out now and land during the collision ----
@@ -392,7 +406,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         // ---- 3. collide the previous plane of the march, zc = z - dir: c_x = 0
         // populations are pushed now, the others go through LDS ----
         const int zc = z - dir;  // plane zc + d sits in LDS slot sl(d)
-        auto sl = [&](int d) { return (k - 1 + dir * d) & 3; };
+        auto sl = [&](int d) { return (k - 1 + dir * d) % NSLOT; };  // k >= 2: never negative
         const uint32_t node = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
         const uint32_t elem = (uint32_t(zc) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(x);
         const uint32_t vo = elem * EB;
@@ -472,9 +486,12 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     }
                     // deviation formats: relative to the destination's density at time n,
                     // rounded as the destination's own thread stores it below
-                    const C dref = DEV ? C(ref_round(float(lds[sl(cz_of(i))][s][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)])))
-                                       : C(0);
-                    const B bits = Prec<P>::enc(pst, w_of<C>(i) * dref);
+                    B bits;
+                    if constexpr (DEV)
+                        bits = Prec<P>::enc_s(
+                            pst, inv_w_of<C>(i) * C(rq[sl(cz_of(i))][s][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)]));
+                    else
+                        bits = Prec<P>::enc(pst, C(0));
                     if (cx_of(i) != 0) {
                         xq[s][xslot_of(i)][ly][lx + 1] = bits;
                         // periodic rows held whole: the wrap across the box's x faces
@@ -531,8 +548,12 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
                 const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
                 // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
-                const R fref = DEV ? R(ref_round(float(lds[sl(czv)][s][ly + 1 + cyv][fx - x0 + 1]))) : R(0);
-                xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = Prec<P>::enc(geq, wgt * fref);
+                B gbits;
+                if constexpr (DEV)
+                    gbits = Prec<P>::enc_s(geq, (m == 0 ? R(18) : R(36)) * R(rq[sl(czv)][s][ly + 1 + cyv][fx - x0 + 1]));
+                else
+                    gbits = Prec<P>::enc(geq, R(0));
+                xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = gbits;
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
             // the directions whose source lies outside the box in y or z, edges
@@ -555,8 +576,12 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     const R wgt = i < 7 ? R(1) / R(18) : R(1) / R(36);
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
-                        const R oref = DEV ? R(ref_round(float(lds[sl(0)][s][ly + 1][lx + 1]))) : R(0);
-                        Prec<P>::bstore(rd[s], vo + uint32_t(i) * plane_bytes, 0, wgt * rhob[s] * br, wgt * oref);
+                        B gb;
+                        if constexpr (DEV)
+                            gb = Prec<P>::enc_s(wgt * rhob[s] * br, (i < 7 ? R(18) : R(36)) * R(rq[sl(0)][s][ly + 1][lx + 1]));
+                        else
+                            gb = Prec<P>::enc(wgt * rhob[s] * br, R(0));
+                        Prec<P>::bstore_bits(rd[s], vo + uint32_t(i) * plane_bytes, 0, gb);
                     }
                 }
             }

@@ -37,7 +37,11 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
     constexpr int LW = TXW + 2;
     constexpr uint32_t EB = 2;
     typedef uint32_t __attribute__((may_alias)) u32a;
-    __shared__ R lds[4][2][TY + 2][LW];
+    // densities of the planes zc - 1, zc, zc + 1 and the reciprocals of their
+    // rounded reference densities (as k_step's deviation formats)
+    constexpr int NSLOT = 3;
+    __shared__ R lds[NSLOT][2][TY + 2][LW];
+    __shared__ float rq[NSLOT][2][TY + 2][LW];
     // every direction's post-collision value by node: node n in column n for the
     // directions with c_x = 0, in column n + 1 for the others, whose columns 0 and
     // tw + 1 hold what streams in across the tile's left and right edges.  The
@@ -154,11 +158,12 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
     uint32_t fprev[2][Q], fcur[2][Q], rprev[2] = {0u, 0u}, rcur[2] = {0u, 0u};
     for (int k = 0; k < nplanes; ++k) {
         const int z = zfirst + dir * k;
-        const int slot = k & 3;
+        const int slot = k % NSLOT;
         if constexpr (kDebugFill) {
             // debug build: this plane's density slot and the exchange buffer start as NaN
             __syncthreads();
             lds_fill(&lds[slot][0][0][0], 2 * (TY + 2) * LW, R(__builtin_nanf("")), tid, 64 * WX * TY);
+            lds_fill(&rq[slot][0][0][0], 2 * (TY + 2) * LW, __builtin_nanf(""), tid, 64 * WX * TY);
             lds_fill(&xq[0][0][0][0], 2 * Q * TY * LW, nan_bits<unsigned short>(P), tid, 64 * WX * TY);
             __syncthreads();
         }
@@ -175,8 +180,12 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
         if (valid) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                lds[slot][0][ly + 1][1 + n0 + j] = own_in ? pair_node_density(fcur[0], rcur[0], j) : rhob[0];
-                lds[slot][1][ly + 1][1 + n0 + j] = own_in ? pair_node_density(fcur[1], rcur[1], j) : rhob[1];
+                const R d0 = own_in ? pair_node_density(fcur[0], rcur[0], j) : rhob[0];
+                const R d1 = own_in ? pair_node_density(fcur[1], rcur[1], j) : rhob[1];
+                lds[slot][0][ly + 1][1 + n0 + j] = d0;
+                lds[slot][1][ly + 1][1 + n0 + j] = d1;
+                rq[slot][0][ly + 1][1 + n0 + j] = ref_rcp(d0);
+                rq[slot][1][ly + 1][1 + n0 + j] = ref_rcp(d1);
             }
         }
         // ring rows y0 - 1 and y0 + th as pairs (threads 0 .. TXW - 1), the two ring
@@ -213,6 +222,8 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
                 for (int j = 0; j < 2; ++j) {
                     lds[slot][0][rsy][1 + 2 * p + j] = rr[j][0];
                     lds[slot][1][rsy][1 + 2 * p + j] = rr[j][1];
+                    rq[slot][0][rsy][1 + 2 * p + j] = ref_rcp(rr[j][0]);
+                    rq[slot][1][rsy][1 + 2 * p + j] = ref_rcp(rr[j][1]);
                 }
             }
         } else if (tid < TXW + 2 * (th + 2)) {
@@ -242,6 +253,8 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
             }
             lds[slot][0][rsy][rsx] = rr[0];
             lds[slot][1][rsy][rsx] = rr[1];
+            rq[slot][0][rsy][rsx] = ref_rcp(rr[0]);
+            rq[slot][1][rsy][rsx] = ref_rcp(rr[1]);
         }
         __syncthreads();
         // ---- 2. the next plane's loads land during the collision ----
@@ -249,7 +262,7 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
         if (k >= 2) {
         // ---- 3. collide plane zc = z - dir, node by node; every value goes to LDS ----
         const int zc = z - dir;
-        auto sl = [&](int d) { return (k - 1 + dir * d) & 3; };
+        auto sl = [&](int d) { return (k - 1 + dir * d) % NSLOT; };  // k >= 2: never negative
         const uint32_t nda = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(xa);
         const uint32_t vo = ((uint32_t(zc) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(xa)) * EB;
         const bool ylo = y == 0, yhi = y == ny - 1;
@@ -319,8 +332,8 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
                         C pst = fi + om * (geq - fi);
                         if (i == 0) pst = C(rho[s]) - psum;
                         else psum += pst;
-                        const C dref = C(ref_round(float(lds[sl(cz_of(i))][s][ly + 1 + cy_of(i)][1 + nn + cx_of(i)])));
-                        const unsigned short bits = (unsigned short)Prec<P>::enc(pst, w_of<C>(i) * dref);
+                        const C scale = inv_w_of<C>(i) * C(rq[sl(cz_of(i))][s][ly + 1 + cy_of(i)][1 + nn + cx_of(i)]);
+                        const unsigned short bits = (unsigned short)Prec<P>::enc_s(pst, scale);
                         xq[s][i][ly][col0(i) + nn] = bits;
                         if (cx_of(i) != 0 && !GHOST && span) {
                             if (cx_of(i) > 0 && nn == tw - 1) xq[s][i][ly][0] = bits;
@@ -359,8 +372,8 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
                 const R usq = gx * gx + gy * gy + gz * gz;
                 const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
                 const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
-                const R fref = R(ref_round(float(lds[sl(czv)][s][ly + 1 + cyv][fx - x0 + 1])));
-                xq[s][idx][ly][side ? tw + 1 : 0] = (unsigned short)Prec<P>::enc(geq, wgt * fref);
+                const R gscale = (m == 0 ? R(18) : R(36)) * R(rq[sl(czv)][s][ly + 1 + cyv][fx - x0 + 1]);
+                xq[s][idx][ly][side ? tw + 1 : 0] = (unsigned short)Prec<P>::enc_s(geq, gscale);
             }
             // (b) y and z faces: the directions whose source lies outside the box in y
             // or z, for both nodes of the pair (the same directions), one 32-bit store
@@ -384,8 +397,8 @@ __global__ __launch_bounds__(64 * WX * TY, 2) void k_step_pair(StepArgs a) {
                         const R br = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq;
 #pragma unroll
                         for (int s = 0; s < 2; ++s) {
-                            const R oref = R(ref_round(float(lds[sl(0)][s][ly + 1][1 + n0 + j])));
-                            word[s] |= uint32_t(Prec<P>::enc(wgt * rhob[s] * br, wgt * oref)) << (16 * j);
+                            const R oscale = (i < 7 ? R(18) : R(36)) * R(rq[sl(0)][s][ly + 1][1 + n0 + j]);
+                            word[s] |= uint32_t(Prec<P>::enc_s(wgt * rhob[s] * br, oscale)) << (16 * j);
                         }
                     }
 #pragma unroll
