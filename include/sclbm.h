@@ -63,8 +63,10 @@ typedef enum {
 typedef enum {
     SCLBM_F64 = 0,     /* FP64 populations, FP64 arithmetic */
     SCLBM_F32 = 1,     /* FP32 populations, FP32 arithmetic (force-stencil densities summed in FP64) */
-    SCLBM_F16DEV = 2,  /* FP16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
-    SCLBM_BF16DEV = 3, /* BF16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic */
+    SCLBM_F16DEV = 2,  /* FP16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic;
+                          both components of a population share a 32-bit word */
+    SCLBM_BF16DEV = 3, /* BF16 relative deviations f_i / (w_i rho_ref) - 1, FP32 arithmetic;
+                          both components of a population share a 32-bit word */
     SCLBM_F32D = 4     /* FP32 populations, FP64 arithmetic: only the storage rounds (slower) */
 } sclbm_prec;
 
@@ -271,21 +273,13 @@ sclbm_status sclbm_save(sclbm_ctx *ctx, void *host_buf, size_t bytes);
 sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
 
 /* Launch shape of the step kernel: a tile of tile_rows rows of tile_waves
- * 64-node columns, (tile_rows, tile_waves) one of (4, 1), (8, 1), (4, 2), and
- * (4, 4) with the 16-bit deviation formats and an even nx; and
+ * 64-node columns, (tile_rows, tile_waves) one of (4, 1), (8, 1), (4, 2); and
  * planes per z-chunk (>= 1).  A tile as wide as the box's rows lets every
  * x-shifted store write whole cache lines; the default is (4, 2) for nx > 64,
  * else (8, 1), and (8, 1) also where the last 128-wide tile of a row would be
- * at most half full (nx mod 128 in 1..64; FP64 and FP32 only).  With the
- * 16-bit deviation formats and an even nx, the (4, 2) and (4, 4) tiles run
- * one or two wavefronts per row whose lanes own two neighbouring nodes each
- * (32-bit accesses of population pairs); (4, 4) is their default where
- * nx > 128 and the last 256-wide tile of a row is full or holds more than
- * 160 nodes.  The default z-chunk minimises
- * (rounds of resident workgroups) x (planes per chunk + 2) for one-node
- * tiles, and fills the device about four times over in chunks of at least
- * 8 planes for two-node tiles.  The shape only changes speed, never
- * results.  Pointers of get_launch may be NULL. */
+ * at most half full (nx mod 128 in 1..64).  The default z-chunk minimises
+ * (rounds of resident workgroups) x (planes per chunk + 2).  The shape only
+ * changes speed, never results.  Pointers of get_launch may be NULL. */
 sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk, int32_t tile_waves);
 sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);
 
@@ -295,8 +289,7 @@ sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t 
 sclbm_status sclbm_default_launch(const sclbm_config *cfg, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);
 
 /* Autotuner: time trial_steps steps (after one warm-up step) for every tile
- * shape ((4, 1), (8, 1), (4, 2) when nx > 64, and (4, 4) where it is valid
- * and nx > 128) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz, and the
+ * shape ((4, 1), (8, 1), (4, 2) when nx > 64) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz, and the
  * tile's default z-chunk, so the default launch is one of the candidates),
  * keep the fastest and set it.  The output pointers
  * (may be NULL) receive its shape and the best average step time in ms.

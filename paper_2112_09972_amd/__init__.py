@@ -466,7 +466,7 @@ class Lattice:
         an init).  Results are cached in $XDG_CACHE_HOME/sclbm/tuning.json keyed
         by device, box shape, boxes, precision and boundary mode."""
         import json
-        key = "%s|%dx%dx%d|%d|%d|%d|rowtiles3" % (self.torch.cuda.get_device_properties(self.device).name, self.nx,
+        key = "%s|%dx%dx%d|%d|%d|%d|rowtiles4" % (self.torch.cuda.get_device_properties(self.device).name, self.nx,
                                                  self.ny, self.nz, self.nbox, self.cfg.prec, self.cfg.bc)
         path = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "sclbm", "tuning.json")
         table = {}
@@ -561,8 +561,7 @@ class Lattice:
 
     def set_launch(self, tile_rows, zchunk, tile_waves=1):
         """Step-kernel tile of tile_rows rows x tile_waves 64-node columns and
-        z-chunk of zchunk planes; (tile_rows, tile_waves) in (4, 1), (8, 1), (4, 2),
-        and (4, 4) for the 16-bit formats with an even nx.
+        z-chunk of zchunk planes; (tile_rows, tile_waves) in (4, 1), (8, 1), (4, 2).
         Speed only: results are bitwise the same for every shape."""
         sclbm_set_launch(self.ctx, tile_rows, zchunk, tile_waves)
 

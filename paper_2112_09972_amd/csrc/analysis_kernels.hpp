@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_reinject(typename Prec<P>::S *f, __half
         node_moments<P>(f, ref, g, k, rho, j);
         if (!(rho[0] > rho[1])) continue;
         if (Prec<P>::DEV) {
-            ref_store(ref + k, float(double(ref_load(ref + k)) * scale));
+            ref_store(ref + ref_index(k, 0), float(double(ref_load(ref + ref_index(k, 0))) * scale));
         } else {
             const int64_t e = pop_base(g, k);
 #pragma unroll

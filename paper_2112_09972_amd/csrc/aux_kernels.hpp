@@ -93,13 +93,13 @@ __global__ __launch_bounds__(256) void k_init(typename Prec<P>::S *f, __half *re
     for (int s = 0; s < 2; ++s) {
         double rref = 0.0;
         if (Prec<P>::DEV) {
-            ref_store(ref + s * g.nnode + k, float(rr[s]));
-            rref = ref_load(ref + s * g.nnode + k);
+            ref_store(ref + ref_index(k, s), float(rr[s]));
+            rref = ref_load(ref + ref_index(k, s));
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const double fe = equilibrium<double>(i, rr[s], ux, uy, uz, usq);
-            Prec<P>::store(f + (int64_t)s * Q * g.nnode + e + (int64_t)i * g.nx, R(fe), R(w_of<R>(i) * R(rref)));
+            Prec<P>::store(f + pop_index<P>(g.nnode, e + (int64_t)i * g.nx, s), R(fe), R(w_of<R>(i) * R(rref)));
         }
     }
 }
@@ -114,10 +114,10 @@ __device__ __forceinline__ void node_moments(const typename Prec<P>::S *f, const
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-        const R rref = Prec<P>::DEV ? R(ref_load(ref + s * N + k)) : R(0);
+        const R rref = Prec<P>::DEV ? R(ref_load(ref + ref_index(k, s))) : R(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const double v = double(Prec<P>::load(f + (int64_t)s * Q * N + e + (int64_t)i * g.nx, w_of<R>(i) * rref));
+            const double v = double(Prec<P>::load(f + pop_index<P>(N, e + (int64_t)i * g.nx, s), w_of<R>(i) * rref));
             r += v;
             if (cx_of(i)) jx += double(cx_of(i)) * v;
             if (cy_of(i)) jy += double(cy_of(i)) * v;

@@ -179,41 +179,17 @@ template <>
 struct Prec<SCLBM_F32> : PrecF32<float> {};
 template <>
 struct Prec<SCLBM_F32D> : PrecF32<double> {};
+// The deviation formats as the auxiliary kernels (initialisation, fields,
+// moments) read and write them, one population at a time; the step kernel
+// (k_step_dev) has its own arithmetic on the stored deviations.
 template <>
 struct Prec<SCLBM_F16DEV> {
     static constexpr bool DEV = true;
     using S = __half;
     using W = float;
     using R = float;
-    using D = float;
     static __device__ __forceinline__ W load(const S *p, R wref) { return wref + wref * __half2float(*p); }
     static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2half_rn(rel_dev(v, wref)); }
-    static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {
-        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-        return wref + wref * __half2float(__builtin_bit_cast(__half, b));
-    }
-    using B = uint32_t;  // the 16 stored bits in the low half
-    using L = unsigned short;
-    template <int AUX = 0>
-    static __device__ __forceinline__ L bload_raw(rsrc_t r, uint32_t vo, uint32_t so) {
-        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, AUX);
-    }
-    static __device__ __forceinline__ W dec(L raw, R wref) {
-        return wref + wref * __half2float(__builtin_bit_cast(__half, raw));
-    }
-    static __device__ __forceinline__ B enc(R v, R wref) {
-        return __builtin_bit_cast(unsigned short, __float2half_rn(rel_dev(v, wref)));
-    }
-    // the same deviation from a precomputed scale s = 1 / wref: v s - 1, one rounding
-    static __device__ __forceinline__ B enc_s(R v, R s) {
-        return __builtin_bit_cast(unsigned short, __float2half_rn(__builtin_fmaf(v, s, -1.0f)));
-    }
-    static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)b, r, vo, so, kStoreNT);
-    }
-    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
-        bstore_bits(r, vo, so, enc(v, wref));
-    }
 };
 template <>
 struct Prec<SCLBM_BF16DEV> {
@@ -221,34 +197,8 @@ struct Prec<SCLBM_BF16DEV> {
     using S = __hip_bfloat16;
     using W = float;
     using R = float;
-    using D = float;
     static __device__ __forceinline__ W load(const S *p, R wref) { return wref + wref * __bfloat162float(*p); }
     static __device__ __forceinline__ void store(S *p, R v, R wref) { *p = __float2bfloat16(rel_dev(v, wref)); }
-    static __device__ __forceinline__ W bload(rsrc_t r, uint32_t vo, uint32_t so, R wref) {
-        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0);
-        return wref + wref * __bfloat162float(__builtin_bit_cast(__hip_bfloat16, b));
-    }
-    using B = uint32_t;
-    using L = unsigned short;
-    template <int AUX = 0>
-    static __device__ __forceinline__ L bload_raw(rsrc_t r, uint32_t vo, uint32_t so) {
-        return __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, AUX);
-    }
-    static __device__ __forceinline__ W dec(L raw, R wref) {
-        return wref + wref * __bfloat162float(__builtin_bit_cast(__hip_bfloat16, raw));
-    }
-    static __device__ __forceinline__ B enc(R v, R wref) {
-        return __builtin_bit_cast(unsigned short, __float2bfloat16(rel_dev(v, wref)));
-    }
-    static __device__ __forceinline__ B enc_s(R v, R s) {
-        return __builtin_bit_cast(unsigned short, __float2bfloat16(__builtin_fmaf(v, s, -1.0f)));
-    }
-    static __device__ __forceinline__ void bstore_bits(rsrc_t r, uint32_t vo, uint32_t so, B b) {
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)b, r, vo, so, kStoreNT);
-    }
-    static __device__ __forceinline__ void bstore(rsrc_t r, uint32_t vo, uint32_t so, R v, R wref) {
-        bstore_bits(r, vo, so, enc(v, wref));
-    }
 };
 
 // Per-node reference densities of the deviation formats (FP16; only their
@@ -256,16 +206,19 @@ struct Prec<SCLBM_BF16DEV> {
 __device__ __forceinline__ float ref_load(const __half *p) { return __half2float(*p); }
 __device__ __forceinline__ float ref_round(float v) { return __half2float(__float2half_rn(v)); }
 __device__ __forceinline__ void ref_store(__half *p, float v) { *p = __float2half_rn(v); }
-// Reciprocal of a node's reference density as the step kernels encode against it:
-// computed once per node and plane and kept in LDS beside the density, so that the
-// encoding of a population pushed into the node is one multiply-add (the same
-// function everywhere, so a node's value does not depend on which tile computed it).
-__device__ __forceinline__ float ref_rcp(float rho) { return __builtin_amdgcn_rcpf(ref_round(rho)); }
-// 1 / w_i, exact: 3, 18, 36
-template <typename R>
-__host__ __device__ constexpr R inv_w_of(int i) {
-    return i == 0 ? R(3) : (i < 7 ? R(18) : R(36));
+
+// Population layout within one box of N nodes, by element of the format's stored
+// type S: e is the row-blocked index ((z ny + y) 19 + i) nx + x of direction i at a
+// node.  FP64 and FP32 keep one array per component, [component][z][y][i][x]; the
+// deviation formats keep both components of (node, i) side by side in one 32-bit
+// word, A first: [z][y][i][x][component].  Their reference densities likewise,
+// [node][component].
+template <int P>
+__host__ __device__ __forceinline__ int64_t pop_index(int64_t N, int64_t e, int s) {
+    if constexpr (Prec<P>::DEV) return 2 * e + s;
+    else return int64_t(s) * Q * N + e;
 }
+__host__ __device__ __forceinline__ int64_t ref_index(int64_t k, int s) { return 2 * k + s; }
 
 inline bool is_dev(int prec) { return prec == SCLBM_F16DEV || prec == SCLBM_BF16DEV; }
 

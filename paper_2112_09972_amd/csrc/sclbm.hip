@@ -18,7 +18,7 @@
 #include "mm_kernel.hpp"
 #include "sclbm.h"
 #include "step_kernel.hpp"
-#include "step_pair_kernel.hpp"
+#include "step_dev_kernel.hpp"
 
 using namespace sclbm;
 
@@ -74,9 +74,10 @@ bool config_ok(const sclbm_config *c, std::string &why) {
     if (c->table_len < 0) { why = "table_len must be >= 0"; return false; }
     const double nodes = double(c->nx) * c->ny * c->nz * c->nbox;
     if (nodes * 2 * Q * elem_bytes(c->prec) > 250e9) { why = "populations exceed 250 GB"; return false; }
-    // the step kernel addresses one component of one box through a raw buffer (32-bit byte offsets)
-    if (double(c->nx) * c->ny * c->nz * Q * elem_bytes(c->prec) >= 4294901760.0) {
-        why = "one box's populations of one component exceed 4 GiB";
+    // the step kernel addresses one component of one box (both, in the deviation
+    // formats' shared words) through a raw buffer (32-bit byte offsets)
+    if (double(c->nx) * c->ny * c->nz * Q * elem_bytes(c->prec) * (is_dev(c->prec) ? 2 : 1) >= 4294901760.0) {
+        why = "one box's populations of one component (both, 16-bit formats) exceed 4 GiB";
         return false;
     }
     return true;
@@ -194,59 +195,44 @@ sclbm_status check_box(const sclbm_ctx *c, int32_t box, bool allow_all) {
     return SCLBM_OK;
 }
 
-// Tile shapes of the step kernel: (rows, 64-node columns).  (4, 4), 256 nodes
-// wide, exists only for the two-nodes-per-lane kernel of the 16-bit formats.
-bool valid_tile(const sclbm_config &c, int ty, int wx) {
-    if (ty == 4 && wx == 4) return is_dev(c.prec) && c.nx % 2 == 0;
+// Waves per SIMD the 16-bit formats' step kernel is compiled for (at most 128 VGPRs).
+constexpr int kDevWaves = 4;
+
+// Tile shapes of the step kernels: (rows, 64-node columns).
+bool valid_tile(const sclbm_config & /*c*/, int ty, int wx) {
     return (ty == 4 && (wx == 1 || wx == 2)) || (ty == 8 && wx == 1);
 }
 
 // Default tile: 128 x 4 (whole 128-wide rows: every x-shifted store writes whole
 // cache lines), unless the last 128-wide tile of a row would be at most half
 // full; then 64 x 8, which leaves fewer idle lanes (measured at 160^3: 402
-// against 463 us per step).  The 16-bit formats take 128 x 4 for any nx > 64,
-// the tile of their two-nodes-per-lane kernel, or 256 x 4 (below).
+// against 463 us per step).
 void default_tile(const sclbm_config &c, int &ty, int &wx) {
     const int tail = c.nx % 128;
-    const bool wide = is_dev(c.prec) ? c.nx > 64 : (c.nx > 64 && (tail == 0 || tail > 64));
+    const bool wide = c.nx > 64 && (tail == 0 || tail > 64);
     wx = wide ? 2 : 1;
     ty = wide ? 4 : 8;
-    // the 16-bit formats: 256-wide tiles of two wavefronts per row where the last
-    // 256-wide tile of a row is full or more than 160 nodes long (FP16, us per
-    // step against 128-wide tiles: 256^3 926 -> 899, 240^3 870 -> 848, 200^3
-    // 615 -> 568, 176^3 461 -> 435; 160^3 406 -> 423 stays on 128-wide tiles)
-    const int tail256 = c.nx % 256;
-    if (valid_tile(c, 4, 4) && c.nx > 128 && (tail256 == 0 || tail256 > 160)) wx = 4;
 }
 
-// Whether a step runs the two-nodes-per-lane kernel (k_step_pair): the 16-bit
-// deviation formats on a 128 x 4 or 256 x 4 tile with an even nx.
-bool uses_pair_kernel(const sclbm_config &c, int ty, int wx) {
-    return is_dev(c.prec) && ty == 4 && (wx == 2 || wx == 4) && c.nx % 2 == 0;
-}
-
-// z-chunk of a launch.  Two waves per SIMD are resident (the register budget):
-// 256 CUs x 4 SIMDs x 2 = 2048 waves = 2048 / (TY WX) workgroups at a time.  A
-// workgroup's time grows with its planes plus the two it reads beyond its chunk,
-// so the one-node kernel takes the chunk count that minimises (rounds of
-// resident workgroups) x (planes per chunk + 2): a grid slightly larger than the
-// device would otherwise take a second, nearly empty round (measured: 160^3 at
-// 5.4 GLUPS with 320 workgroups).  The pair kernel runs best with about four
-// rounds of resident workgroups and chunks of at least 8 planes (measured on
-// 128^3 and 256^3 boxes: 16 chunks in z in both); its 128-wide tiles (4
-// wavefronts, 64 KB of LDS) have 512 resident workgroups, its 256-wide tiles
-// (8 wavefronts, 128 KB) 256.
+// z-chunk of a launch.  FP64 and FP32: two waves per SIMD are resident (the
+// register budget): 256 CUs x 4 SIMDs x 2 = 2048 waves = 2048 / (TY WX)
+// workgroups at a time.  A workgroup's time grows with its planes plus the two it
+// reads beyond its chunk, so the launch takes the chunk count that minimises
+// (rounds of resident workgroups) x (planes per chunk + 2): a grid slightly
+// larger than the device would otherwise take a second, nearly empty round
+// (measured: 160^3 at 5.4 GLUPS with 320 workgroups).  The 16-bit formats: four
+// waves per SIMD, and chunks of at most 32 planes (measured at 256^3, FP16 on
+// 128 x 4 tiles, us per step: chunks of 16 / 32 / 64 734 / 735 / 775; the
+// rule's unbounded choice is 64).
 int default_zchunk(const sclbm_config &c, int ty, int wx) {
     const long tiles = long((c.nx + 64 * wx - 1) / (64 * wx)) * long((c.ny + ty - 1) / ty) * c.nbox;
-    if (uses_pair_kernel(c, ty, wx)) {
-        const long four_rounds = 4L * (wx == 4 ? 256 : 512);
-        const long zc = (tiles * c.nz + four_rounds - 1) / four_rounds;
-        return int(std::max(std::min(8L, long(c.nz)), std::min(zc, long(c.nz))));
-    }
-    const long resident = 2048 / (ty * wx);
-    long best_cost = -1, best_zc = c.nz;
+    const bool dev = is_dev(c.prec);
+    const long resident = (dev ? 1024L * kDevWaves : 2048L) / (ty * wx);
+    const long zmax = dev ? 32 : c.nz;
+    long best_cost = -1, best_zc = std::min<long>(c.nz, zmax);
     for (long nzc = 1; nzc <= std::max(1, c.nz / 2); ++nzc) {
         const long zc = (c.nz + nzc - 1) / nzc;
+        if (zc > zmax) continue;
         const long chunks = (c.nz + zc - 1) / zc;
         const long rounds = (tiles * chunks + resident - 1) / resident;
         const long cost = rounds * (zc + 2);
@@ -265,39 +251,23 @@ hipError_t launch_step_tile(sclbm_ctx *c, const StepArgs &a) {
     dim3 grid((c->cfg.nx + 64 * WX - 1) / (64 * WX), (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
     // register budget: two waves per SIMD (up to 256 VGPRs); a tighter budget spills
     constexpr int WAVES = 2;
-    if (c->cfg.bc == SCLBM_BC_GHOST)
-        hipLaunchKernelGGL((k_step<P, TY, WX, true, WAVES>), grid, block, 0, c->stream, a);
-    else
-        hipLaunchKernelGGL((k_step<P, TY, WX, false, WAVES>), grid, block, 0, c->stream, a);
+    if constexpr (Prec<P>::DEV) {
+        // the 16-bit formats fit four waves per SIMD (128 VGPRs)
+        if (c->cfg.bc == SCLBM_BC_GHOST)
+            hipLaunchKernelGGL((k_step_dev<P, TY, WX, true, kDevWaves>), grid, block, 0, c->stream, a);
+        else
+            hipLaunchKernelGGL((k_step_dev<P, TY, WX, false, kDevWaves>), grid, block, 0, c->stream, a);
+    } else {
+        if (c->cfg.bc == SCLBM_BC_GHOST)
+            hipLaunchKernelGGL((k_step<P, TY, WX, true, WAVES>), grid, block, 0, c->stream, a);
+        else
+            hipLaunchKernelGGL((k_step<P, TY, WX, false, WAVES>), grid, block, 0, c->stream, a);
+    }
     return hipGetLastError();
-}
-
-// The 16-bit deviation formats on a 128 x 4 (256 x 4) tile with an even nx: one
-// (two) wavefront(s) per row, two nodes per lane (same results, half the memory
-// instructions).
-template <int P, int WX>
-hipError_t launch_step_pair_w(sclbm_ctx *c, const StepArgs &a) {
-    constexpr int TY = 4;
-    dim3 block(64 * WX, TY, 1);
-    dim3 grid((c->cfg.nx + 128 * WX - 1) / (128 * WX), (c->cfg.ny + TY - 1) / TY, a.nzc * c->cfg.nbox);
-    if (c->cfg.bc == SCLBM_BC_GHOST)
-        hipLaunchKernelGGL((k_step_pair<P, TY, WX, true>), grid, block, 0, c->stream, a);
-    else
-        hipLaunchKernelGGL((k_step_pair<P, TY, WX, false>), grid, block, 0, c->stream, a);
-    return hipGetLastError();
-}
-
-template <int P>
-hipError_t launch_step_pair(sclbm_ctx *c, const StepArgs &a) {
-    if (c->tile_waves == 4) return launch_step_pair_w<P, 2>(c, a);
-    return launch_step_pair_w<P, 1>(c, a);
 }
 
 template <int P>
 hipError_t launch_step(sclbm_ctx *c, const StepArgs &a) {
-    if constexpr (Prec<P>::DEV) {
-        if (uses_pair_kernel(c->cfg, c->tile_rows, c->tile_waves)) return launch_step_pair<P>(c, a);
-    }
     if (c->tile_waves == 2) return launch_step_tile<P, 4, 2>(c, a);
     if (c->tile_rows == 8) return launch_step_tile<P, 8, 1>(c, a);
     return launch_step_tile<P, 4, 1>(c, a);
@@ -813,10 +783,10 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
     int bty = ty_keep, bwx = wx_keep, bzc = zc_keep;
     // candidates: every valid tile with z-chunks 2 .. 64 (capped at nz) and the
     // tile's default z-chunk, so that the default launch is always among them
-    const int tys[4] = {4, 8, 4, 4}, wxs[4] = {1, 1, 2, 4};
+    const int tys[3] = {4, 8, 4}, wxs[3] = {1, 1, 2};
     const int zcs[6] = {2, 4, 8, 16, 32, 64};
     std::vector<std::array<int, 3>> cand;
-    for (int ti = 0; ti < 4; ++ti) {
+    for (int ti = 0; ti < 3; ++ti) {
         if (!valid_tile(c->cfg, tys[ti], wxs[ti])) continue;
         if (c->cfg.nx <= 64 * (wxs[ti] / 2)) continue;  // the tile's last column would hold no nodes
         std::vector<int> zl;
@@ -1184,7 +1154,7 @@ sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk, i
     if (st) return st;
     if (!valid_tile(c->cfg, tile_rows, tile_waves))
         return fail(SCLBM_EINVAL,
-                    "tile (rows %d, waves %d) must be (4, 1), (8, 1), (4, 2), or (4, 4) with a 16-bit format and even nx",
+                    "tile (rows %d, waves %d) must be (4, 1), (8, 1) or (4, 2)",
                     tile_rows, tile_waves);
     if (zchunk < 1) return fail(SCLBM_EINVAL, "zchunk must be >= 1");
     c->tile_rows = tile_rows;

@@ -1,6 +1,7 @@
 // Fused stream-and-collide step of the two-component Shan-Chen model
 // (arXiv 2112.09972, Sec. 2 Eqs. 6-9, ghost boundary of Sec. 2 Eq. 8 and Sec. 3
-// Eq. 14) for gfx950.
+// Eq. 14) for gfx950: FP64 and FP32 storage (the 16-bit deviation formats run
+// k_step_dev, which shares the tiling, march and stores described here).
 //
 // State: f(n), the populations of both components after streaming, in
 // row-blocked SoA order [box][component][z][y][direction][x]: for every (y, z)
@@ -20,7 +21,7 @@
 // plane z needs the densities of planes
 // z-1, z, z+1 including a one-node ring around the tile; those densities live in
 // a 4-slot rolling buffer in LDS.  Per plane each thread takes its node's 38
-// populations into a register window (FP32 and 16-bit storage: loaded during the
+// populations into a register window (FP32 storage: loaded during the
 // previous plane's collision) and sums them into densities, the workgroup adds the ring
 // densities, and after a barrier the previous plane's window is collided.
 // Ring densities (and the two chunk-end planes) are recomputed rather than
@@ -35,8 +36,8 @@
 // the same access pattern without arithmetic runs at 3.7 TB/s with shifted
 // stores and 5.1 TB/s with whole-line ones.)  Stores are non-temporal.
 //
-// Precision.  FP64 storage computes in FP64.  FP32 and the 16-bit formats
-// compute the collision in FP32; with FP32 storage the densities of the force
+// Precision.  FP64 storage computes in FP64.  FP32 storage computes the
+// collision in FP32 (or FP64: SCLBM_F32D); the densities of the force
 // stencil are summed in FP64 (from the FP32 populations, so exactly up to the
 // storage rounding): the stencil takes differences of neighbouring densities,
 // and an FP32 sum leaves a rounding noise of a few 1e-7 in them that the
@@ -73,7 +74,8 @@ struct StepArgs {
     double tau[2];
     double g;                 // G_AB
     double rho_b[2];          // ghost densities
-    const __half *ref_src;    // deviation formats: per-node reference densities of f(n) [box][2][N]
+    const __half *ref_src;    // deviation formats: per-node reference densities of f(n),
+                              // [box][node][component]
     __half *ref_dst;          // and of f(n+1); unused otherwise
     double xc[3];             // box centre
 };
@@ -181,12 +183,10 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     // that nothing waits for them during the collision) are loaded while the
     // current one collides.  FP64 windows leave no registers for a third plane.
     constexpr bool PREFETCH = sizeof(S) < 8;
-    // density window: the planes zc - 1, zc, zc + 1 of the collision (slots of the
-    // march); FP32/FP64 keep a fourth slot, the deviation formats use that room for
-    // the reciprocal reference densities of the same planes (rq)
-    constexpr int NSLOT = Prec<P>::DEV ? 3 : 4;
+    static_assert(!Prec<P>::DEV, "the 16-bit deviation formats run k_step_dev");
+    // density window: the planes zc - 1, zc, zc + 1 of the collision and one more
+    constexpr int NSLOT = 4;
     __shared__ D lds[NSLOT][2][TY + 2][LW];
-    __shared__ float rq[Prec<P>::DEV ? NSLOT : 1][2][Prec<P>::DEV ? TY + 2 : 1][Prec<P>::DEV ? LW : 1];
     // x exchange: post-collision values with c_x != 0, by component, slot, row and
     // column lx + 1; columns 0 and tw + 1 hold what streams in across the tile's
     // left and right edges (ghost populations, or the periodic wrap)
@@ -242,9 +242,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     const int64_t n = *a.clk_in;
     if (lin == 0 && tid == 0) *a.clk_out = n + 1;
 
-    constexpr bool DEV = Prec<P>::DEV;
-    const __half *ref_in = DEV ? a.ref_src + (int64_t)box * 2 * N : nullptr;
-    __half *ref_out = DEV ? a.ref_dst + (int64_t)box * 2 * N : nullptr;
     const R rhob[2] = {R(a.rho_b[0]), R(a.rho_b[1])};
     const D rhobd[2] = {D(a.rho_b[0]), D(a.rho_b[1])};
     // velocity gradient of step n (ghost mode), read before the first store so
@@ -273,9 +270,8 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         nd = uint32_t(zz) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
         return in && valid;
     };
-    // raw words of the next plane and, for the deviation formats, its reference densities
+    // raw words of the next plane
     L fnx[2][Q];
-    __half rnx[2] = {__half(0.0f), __half(0.0f)};
     bool nx_in = false;
     // rows that no other workgroup reads: not a tile edge row in y, not a chunk-end
     // plane, in a ghost-mode tile holding whole rows (no ring columns taken from it)
@@ -287,7 +283,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             const bool once = row_once && z > zs && z < ze - 1;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-                if (DEV) rnx[s] = ref_in[s * N + nd];
                 if (once) {
 #pragma unroll
                     for (int i = 0; i < Q; ++i)
@@ -311,7 +306,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             // debug build: this plane's density slot and the exchange buffer start as NaN
             __syncthreads();
             lds_fill(&lds[slot][0][0][0], 2 * (TY + 2) * LW, D(__builtin_nan("")), tid, 64 * WX * TY);
-            if (Prec<P>::DEV) lds_fill(&rq[slot][0][0][0], 2 * (TY + 2) * LW, __builtin_nanf(""), tid, 64 * WX * TY);
             lds_fill(&xq[0][0][0][0], 2 * NXD * TY * LW, nan_bits<B>(P), tid, 64 * WX * TY);
             __syncthreads();
         }
@@ -324,38 +318,34 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) fcur[s][i] = Prec<P>::dec(fnx[s][i], w_of<R>(i) * R(__half2float(rnx[s])));
+                    for (int i = 0; i < Q; ++i) fcur[s][i] = Prec<P>::dec(fnx[s][i], R(0));
             }
         } else {
             uint32_t own_vo, own_nd;
             own_in = own_node(z, own_vo, own_nd);
             if (own_in) {
 #pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const R rr = DEV ? R(ref_load(ref_in + s * N + own_nd)) : R(0);
+                for (int s = 0; s < 2; ++s)
 #pragma unroll
-                    for (int i = 0; i < Q; ++i)
-                        fcur[s][i] = Prec<P>::bload(rs[s], own_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * rr);
-                }
+                    for (int i = 0; i < Q; ++i) fcur[s][i] = Prec<P>::bload(rs[s], own_vo, uint32_t(i) * plane_bytes, R(0));
             }
         }
         bool ring_on = false, ring_in = false;
-        uint32_t ring_vo = 0, ring_nd = 0;
+        uint32_t ring_vo = 0;
         int rsx = 0, rsy = 0;
         if (tid < ringN) {
+            // threads 0 .. 2 tw - 1: the ring rows y0 - 1 and y0 + th at x0 .. x0 + tw - 1,
+            // lane by lane from x0, so that a wavefront's loads of a ring row cover
+            // whole cache lines as the own row's do; then the two ring columns
+            // x0 - 1 and x0 + tw, corners included, node by node
             const int r = tid;
-            if (r < tw + 2) {
-                rsx = r;
-                rsy = 0;
-            } else if (r < 2 * (tw + 2)) {
-                rsx = r - (tw + 2);
-                rsy = th + 1;
-            } else if (r < 2 * (tw + 2) + th) {
-                rsx = 0;
-                rsy = r - 2 * (tw + 2) + 1;
+            if (r < 2 * tw) {
+                rsy = r < tw ? 0 : th + 1;
+                rsx = (r < tw ? r : r - tw) + 1;
             } else {
-                rsx = tw + 1;
-                rsy = r - 2 * (tw + 2) - th + 1;
+                const int q = r - 2 * tw;  // 0 .. 2 (th + 2) - 1
+                rsx = q < th + 2 ? 0 : tw + 1;
+                rsy = q < th + 2 ? q : q - (th + 2);
             }
             int gx = x0 - 1 + rsx, gy = y0 - 1 + rsy, gz = z;
             ring_in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
@@ -367,37 +357,26 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             }
             ring_on = true;
             ring_vo = ((uint32_t(gz) * uint32_t(ny) + uint32_t(gy)) * qnx + uint32_t(gx)) * EB;
-            ring_nd = uint32_t(gz) * nxy + uint32_t(gy) * uint32_t(nx) + uint32_t(gx);
         }
         if (valid) {
             const D r0 = own_in ? pair_density<D>(fcur[0]) : rhobd[0];
             const D r1 = own_in ? pair_density<D>(fcur[1]) : rhobd[1];
             lds[slot][0][ly + 1][lx + 1] = r0;
             lds[slot][1][ly + 1][lx + 1] = r1;
-            if constexpr (DEV) {
-                rq[slot][0][ly + 1][lx + 1] = ref_rcp(float(r0));
-                rq[slot][1][ly + 1][lx + 1] = ref_rcp(float(r1));
-            }
         }
         if (ring_on) {
             D rr[2] = {rhobd[0], rhobd[1]};
             if (ring_in) {
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
-                    const R ref = DEV ? R(ref_load(ref_in + s * N + ring_nd)) : R(0);
                     W f[Q];
 #pragma unroll
-                    for (int i = 0; i < Q; ++i)
-                        f[i] = Prec<P>::bload(rs[s], ring_vo, uint32_t(i) * plane_bytes, w_of<R>(i) * ref);
+                    for (int i = 0; i < Q; ++i) f[i] = Prec<P>::bload(rs[s], ring_vo, uint32_t(i) * plane_bytes, R(0));
                     rr[s] = pair_density<D>(f);
                 }
             }
             lds[slot][0][rsy][rsx] = rr[0];
             lds[slot][1][rsy][rsx] = rr[1];
-            if constexpr (DEV) {
-                rq[slot][0][rsy][rsx] = ref_rcp(float(rr[0]));
-                rq[slot][1][rsy][rsx] = ref_rcp(float(rr[1]));
-            }
         }
         __syncthreads();
         // ---- 2. the next plane's loads go out now and land during the collision ----
@@ -407,7 +386,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         // populations are pushed now, the others go through LDS ----
         const int zc = z - dir;  // plane zc + d sits in LDS slot sl(d)
         auto sl = [&](int d) { return (k - 1 + dir * d) % NSLOT; };  // k >= 2: never negative
-        const uint32_t node = uint32_t(zc) * nxy + uint32_t(y) * uint32_t(nx) + uint32_t(x);
         const uint32_t elem = (uint32_t(zc) * uint32_t(ny) + uint32_t(y)) * qnx + uint32_t(x);
         const uint32_t vo = elem * EB;
         const bool ylo = y == 0, yhi = y == ny - 1;
@@ -484,14 +462,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                         if (i == 0) pst = C(rho[s]) - psum;
                         else psum += pst;
                     }
-                    // deviation formats: relative to the destination's density at time n,
-                    // rounded as the destination's own thread stores it below
-                    B bits;
-                    if constexpr (DEV)
-                        bits = Prec<P>::enc_s(
-                            pst, inv_w_of<C>(i) * C(rq[sl(cz_of(i))][s][ly + 1 + cy_of(i)][lx + 1 + cx_of(i)]));
-                    else
-                        bits = Prec<P>::enc(pst, C(0));
+                    const B bits = Prec<P>::enc(pst, C(0));
                     if (cx_of(i) != 0) {
                         xq[s][xslot_of(i)][ly][lx + 1] = bits;
                         // periodic rows held whole: the wrap across the box's x faces
@@ -516,7 +487,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     }
                     Prec<P>::bstore_bits(rd[s], dvo, 0, bits);
                 };
-                if (DEV) ref_store(ref_out + s * N + node, float(rho[s]));
                 equilibrium_pairs<C>(ux, uy, uz, r, aa, r3, r45, push);
             }
         }
@@ -548,12 +518,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
                 const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
                 // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
-                B gbits;
-                if constexpr (DEV)
-                    gbits = Prec<P>::enc_s(geq, (m == 0 ? R(18) : R(36)) * R(rq[sl(czv)][s][ly + 1 + cyv][fx - x0 + 1]));
-                else
-                    gbits = Prec<P>::enc(geq, R(0));
-                xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = gbits;
+                xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = Prec<P>::enc(geq, R(0));
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
             // the directions whose source lies outside the box in y or z, edges
@@ -576,12 +541,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     const R wgt = i < 7 ? R(1) / R(18) : R(1) / R(36);
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
-                        B gb;
-                        if constexpr (DEV)
-                            gb = Prec<P>::enc_s(wgt * rhob[s] * br, (i < 7 ? R(18) : R(36)) * R(rq[sl(0)][s][ly + 1][lx + 1]));
-                        else
-                            gb = Prec<P>::enc(wgt * rhob[s] * br, R(0));
-                        Prec<P>::bstore_bits(rd[s], vo + uint32_t(i) * plane_bytes, 0, gb);
+                        Prec<P>::bstore_bits(rd[s], vo + uint32_t(i) * plane_bytes, 0, Prec<P>::enc(wgt * rhob[s] * br, R(0)));
                     }
                 }
             }

@@ -19,8 +19,9 @@ CASES = [
     ("f32", "ghost", (150, 13, 11), (4, 5, 2)), ("f32", "periodic", (45, 13, 11), (4, 5, 2)),
     ("f64", "ghost", (100, 10, 9), (4, 3, 2)), ("f64", "periodic", (100, 10, 9), (8, 4, 1)),
     ("f32d", "ghost", (40, 12, 9), (8, 4, 1)),
-    ("f16dev", "ghost", (150, 13, 11), (4, 5, 2)), ("f16dev", "periodic", (300, 6, 5), (4, 2, 4)),
-    ("f16dev", "ghost", (70, 9, 7), (4, 3, 1)), ("bf16dev", "ghost", (270, 6, 5), (4, 3, 4)),
+    ("f16dev", "ghost", (150, 13, 11), (4, 5, 2)), ("f16dev", "periodic", (300, 6, 5), (8, 2, 1)),
+    ("f16dev", "ghost", (70, 9, 7), (4, 3, 1)), ("bf16dev", "ghost", (270, 6, 5), (4, 3, 2)),
+    ("bf16dev", "ghost", (45, 13, 11), (4, 5, 2)),
     ("bf16dev", "periodic", (46, 6, 5), (4, 3, 2)),
 ]
 

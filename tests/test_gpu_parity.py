@@ -301,8 +301,7 @@ def test_step_past_table_and_mach_errors(sc):
     with pytest.raises(sc.SclbmError) as ei:
         lat.set_gradient_table(np.tile(wl.simple_shear(0.05), (10, 1)), 10)
     assert ei.value.status == sc.SCLBM_EINVAL and "ghost speed" in str(ei.value)
-    # tile shapes outside (4, 1), (8, 1), (4, 2) and z-chunks below 1 are refused;
-    # (4, 4) exists only for the 16-bit formats
+    # tile shapes outside (4, 1), (8, 1), (4, 2) and z-chunks below 1 are refused
     for bad in [(2, 16, 2), (8, 16, 2), (4, 16, 3), (6, 16, 1), (4, 0, 1), (4, 16, 4)]:
         with pytest.raises(sc.SclbmError) as ei:
             lat.set_launch(*bad)
@@ -380,60 +379,17 @@ def test_c1_deviation_formats_500_steps(sc, prec):
     assert abs(d - d_or) <= 2 * DEV_TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
-@pytest.mark.parametrize("bc,nxyz,launch", [("ghost", (150, 13, 11), (4, 5, 2)), ("periodic", (150, 13, 11), (4, 2, 2)),
-                                            ("ghost", (70, 9, 7), (4, 100, 2)), ("periodic", (46, 6, 5), (4, 3, 2)),
-                                            ("ghost", (45, 13, 11), (4, 5, 2)), ("ghost", (150, 13, 11), (4, 5, 4)),
-                                            ("periodic", (150, 13, 11), (4, 2, 4)), ("ghost", (300, 6, 5), (4, 2, 4)),
-                                            ("periodic", (270, 6, 5), (4, 3, 4))])
-def test_two_node_tiles_deviation_formats(sc, prec, bc, nxyz, launch):
-    """The 16-bit formats on a (4, 2) or (4, 4) tile with an even nx run one or
-    two wavefronts per 128- or 256-node row whose lanes own two neighbouring
-    nodes (32-bit population pairs): against the oracle, and bit for bit
-    against 64-node tiles of one node per lane.  nx = 150 on (4, 2): a full and
-    a 22-wide tile (values cross between workgroups); nx = 150 on (4, 4), 70,
-    46: one partial tile holding whole rows (periodic wrap inside it); nx = 300,
-    270 on (4, 4): a full 256-wide tile and a 44- or 14-wide one; ny, nz ragged
-    against the tile height and z-chunk; nx = 45 (odd) runs the one-node
-    kernel at (4, 2)."""
-    A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
-    steps = 20
-    tab = np.tile(A, (steps, 1))
-    out = []
-    for shape in (launch, (4, 3, 1)):
-        lat, o = make_pair(sc, None, nxyz=nxyz, prec=prec, bc=bc, R=4.0, A=A if bc == "ghost" else None,
-                           steps=steps)
-        lat.set_launch(*shape)
-        if nxyz[0] % 2:
-            with pytest.raises(sc.SclbmError) as ei:
-                lat.set_launch(4, 5, 4)  # two nodes per lane need an even nx
-            assert ei.value.status == sc.SCLBM_EINVAL
-        if bc == "ghost":
-            lat.set_gradient_table(tab, 0)
-        lat.step(steps)
-        out.append(lat.save())
-        if shape == launch:
-            o.run(steps, tab if bc == "ghost" else None)
-            err = rel_density_error(lat, o)
-            print("%s %s %s: max rel density error %.3e" % (prec, bc, nxyz, err))
-            assert err <= DEV_TOL[prec]
-        lat.close()
-    assert np.array_equal(out[0][64:], out[1][64:])
+DEV_SHAPES = [("ghost", (150, 13, 11), (4, 5, 2)), ("periodic", (150, 13, 11), (4, 2, 2)),
+              ("ghost", (70, 9, 7), (4, 100, 2)), ("periodic", (46, 6, 5), (4, 3, 2)),
+              ("ghost", (45, 13, 11), (4, 5, 2)), ("ghost", (300, 6, 5), (8, 2, 1)),
+              ("periodic", (270, 6, 5), (4, 3, 2)), ("ghost", (257, 6, 5), (4, 2, 2))]
 
 
-@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
-@pytest.mark.parametrize("bc,nxyz,launch", [("ghost", (150, 13, 11), (4, 5, 2)), ("periodic", (270, 6, 5), (4, 3, 4)),
-                                            ("ghost", (300, 6, 5), (4, 2, 4))])
-def test_two_node_tiles_deviation_formats_tau3(sc, prec, bc, nxyz, launch):
-    """The 16-bit formats at tau = 3 (Table 2; wl.TAU3), where every post-collision
-    value keeps two thirds of the incoming population, so that the pair kernel's
-    decode of f_i at the collision matters: against the oracle, and bit for bit
-    against 64-node tiles of one node per lane."""
+def deviation_tiles_case(sc, prec, bc, nxyz, launch, steps=20, **kw):
+    """Run a 16-bit format at `launch` and on 64 x 4 tiles: the first against the
+    oracle (DEV_TOL), both bit for bit against each other."""
     A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
-    steps = 20
     tab = np.tile(A, (steps, 1))
-    kw = dict(tau=(3.0, 3.0), g=T3["g_ab"], rho_in=T3["rho_hi"], rho_out=T3["rho_lo"],
-              rho_b=(T3["rho_lo"], T3["rho_hi"]))
     out = []
     for shape in (launch, (4, 3, 1)):
         lat, o = make_pair(sc, None, nxyz=nxyz, prec=prec, bc=bc, R=4.0, A=A if bc == "ghost" else None,
@@ -446,10 +402,32 @@ def test_two_node_tiles_deviation_formats_tau3(sc, prec, bc, nxyz, launch):
         if shape == launch:
             o.run(steps, tab if bc == "ghost" else None)
             err = rel_density_error(lat, o)
-            print("%s %s %s tau3: max rel density error %.3e" % (prec, bc, nxyz, err))
+            print("%s %s %s %s: max rel density error %.3e" % (prec, bc, nxyz, kw.get("tau", ""), err))
             assert err <= DEV_TOL[prec]
         lat.close()
     assert np.array_equal(out[0][64:], out[1][64:])
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("bc,nxyz,launch", DEV_SHAPES)
+def test_deviation_formats_tile_shapes(sc, prec, bc, nxyz, launch):
+    """The 16-bit formats (both components of a population in one 32-bit word, one
+    node per lane) on 128-wide and 64 x 8 tiles against the oracle, and bit for bit
+    against 64 x 4 tiles.  nx = 150 on 128-wide tiles: a full and a 22-wide tile
+    (values cross between workgroups); nx = 70, 46: one partial tile holding whole
+    rows (periodic wrap inside it); nx = 45, 257: odd rows; ny, nz ragged against
+    the tile height and z-chunk."""
+    deviation_tiles_case(sc, prec, bc, nxyz, launch)
+
+
+@pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
+@pytest.mark.parametrize("bc,nxyz,launch", [DEV_SHAPES[0], DEV_SHAPES[6], DEV_SHAPES[7]])
+def test_deviation_formats_tile_shapes_tau3(sc, prec, bc, nxyz, launch):
+    """The same at tau = 3 (Table 2; wl.TAU3), where every post-collision value
+    keeps two thirds of the incoming population, so that the stored deviations
+    enter the collision (at tau = 1 they drop out of it)."""
+    deviation_tiles_case(sc, prec, bc, nxyz, launch, tau=(3.0, 3.0), g=T3["g_ab"], rho_in=T3["rho_hi"],
+                         rho_out=T3["rho_lo"], rho_b=(T3["rho_lo"], T3["rho_hi"]))
 
 
 @pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
