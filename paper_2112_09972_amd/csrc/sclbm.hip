@@ -198,8 +198,10 @@ sclbm_status check_box(const sclbm_ctx *c, int32_t box, bool allow_all) {
 // Waves per SIMD the 16-bit formats' step kernel is compiled for (at most 128 VGPRs).
 constexpr int kDevWaves = 4;
 
-// Tile shapes of the step kernels: (rows, 64-node columns).
-bool valid_tile(const sclbm_config & /*c*/, int ty, int wx) {
+// Tile shapes of the step kernels: (rows, 64-node columns).  (4, 4), 256 nodes
+// wide in 16 wavefronts, needs four waves per SIMD: the 16-bit formats only.
+bool valid_tile(const sclbm_config &c, int ty, int wx) {
+    if (ty == 4 && wx == 4) return is_dev(c.prec);
     return (ty == 4 && (wx == 1 || wx == 2)) || (ty == 8 && wx == 1);
 }
 
@@ -212,6 +214,11 @@ void default_tile(const sclbm_config &c, int &ty, int &wx) {
     const bool wide = c.nx > 64 && (tail == 0 || tail > 64);
     wx = wide ? 2 : 1;
     ty = wide ? 4 : 8;
+    // the 16-bit formats: 256-wide tiles where the last 256-wide tile of a row is
+    // full or more than 160 nodes long (no ring columns loaded from a neighbouring
+    // tile of the row: each such node costs 19 cache lines for 76 bytes)
+    const int tail256 = c.nx % 256;
+    if (valid_tile(c, 4, 4) && c.nx > 128 && (tail256 == 0 || tail256 > 160)) wx = 4;
 }
 
 // z-chunk of a launch.  FP64 and FP32: two waves per SIMD are resident (the
@@ -268,6 +275,9 @@ hipError_t launch_step_tile(sclbm_ctx *c, const StepArgs &a) {
 
 template <int P>
 hipError_t launch_step(sclbm_ctx *c, const StepArgs &a) {
+    if constexpr (Prec<P>::DEV) {
+        if (c->tile_waves == 4) return launch_step_tile<P, 4, 4>(c, a);
+    }
     if (c->tile_waves == 2) return launch_step_tile<P, 4, 2>(c, a);
     if (c->tile_rows == 8) return launch_step_tile<P, 8, 1>(c, a);
     return launch_step_tile<P, 4, 1>(c, a);
@@ -783,10 +793,10 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
     int bty = ty_keep, bwx = wx_keep, bzc = zc_keep;
     // candidates: every valid tile with z-chunks 2 .. 64 (capped at nz) and the
     // tile's default z-chunk, so that the default launch is always among them
-    const int tys[3] = {4, 8, 4}, wxs[3] = {1, 1, 2};
+    const int tys[4] = {4, 8, 4, 4}, wxs[4] = {1, 1, 2, 4};
     const int zcs[6] = {2, 4, 8, 16, 32, 64};
     std::vector<std::array<int, 3>> cand;
-    for (int ti = 0; ti < 3; ++ti) {
+    for (int ti = 0; ti < 4; ++ti) {
         if (!valid_tile(c->cfg, tys[ti], wxs[ti])) continue;
         if (c->cfg.nx <= 64 * (wxs[ti] / 2)) continue;  // the tile's last column would hold no nodes
         std::vector<int> zl;
@@ -1154,7 +1164,7 @@ sclbm_status sclbm_set_launch(sclbm_ctx *c, int32_t tile_rows, int32_t zchunk, i
     if (st) return st;
     if (!valid_tile(c->cfg, tile_rows, tile_waves))
         return fail(SCLBM_EINVAL,
-                    "tile (rows %d, waves %d) must be (4, 1), (8, 1) or (4, 2)",
+                    "tile (rows %d, waves %d) must be (4, 1), (8, 1), (4, 2), or (4, 4) with a 16-bit format",
                     tile_rows, tile_waves);
     if (zchunk < 1) return fail(SCLBM_EINVAL, "zchunk must be >= 1");
     c->tile_rows = tile_rows;

@@ -21,7 +21,8 @@ CASES = [
     ("f32d", "ghost", (40, 12, 9), (8, 4, 1)),
     ("f16dev", "ghost", (150, 13, 11), (4, 5, 2)), ("f16dev", "periodic", (300, 6, 5), (8, 2, 1)),
     ("f16dev", "ghost", (70, 9, 7), (4, 3, 1)), ("bf16dev", "ghost", (270, 6, 5), (4, 3, 2)),
-    ("bf16dev", "ghost", (45, 13, 11), (4, 5, 2)),
+    ("bf16dev", "ghost", (45, 13, 11), (4, 5, 2)), ("f16dev", "ghost", (300, 6, 5), (4, 2, 4)),
+    ("bf16dev", "periodic", (257, 6, 5), (4, 3, 4)),
     ("bf16dev", "periodic", (46, 6, 5), (4, 3, 2)),
 ]
 

@@ -88,9 +88,9 @@ def test_ensemble_tau3_boxes_and_totals_match_oracle(sc, prec, tol):
     ens.close()
 
 
-@pytest.mark.parametrize("prec,wide", [("f16dev", 2), ("bf16dev", 2), ("f16dev", 1)])
+@pytest.mark.parametrize("prec,wide", [("f16dev", 2), ("bf16dev", 2), ("f16dev", 1), ("bf16dev", 4)])
 def test_deviation_ensemble_tiles(sc, prec, wide):
-    """16-bit formats on 128 x 4 or 64 x 4 tiles: every box of a 3-box ensemble of
+    """16-bit formats on 128 x 4, 64 x 4 or 256 x 4 tiles: every box of a 3-box ensemble of
     70 x 10 x 9 boxes (three z-chunks per box) gives the same fields, bit for bit,
     as the box run alone on the same tiles and as the box run alone on 64 x 4
     tiles."""
@@ -121,7 +121,7 @@ def test_deviation_ensemble_tiles(sc, prec, wide):
     ens.close()
 
 
-@pytest.mark.parametrize("prec,nx,launch", [("f32", 20, None), ("f16dev", 150, (4, 3, 2)), ("bf16dev", 100, (8, 3, 1))])
+@pytest.mark.parametrize("prec,nx,launch", [("f32", 20, None), ("f16dev", 150, (4, 3, 4)), ("bf16dev", 100, (8, 3, 1))])
 def test_graph_replays_match_eager(sc, prec, nx, launch):
     """A captured 10-step loop replayed five times, with eager work and
     synchronisations between replays, equals eager stepping after every replay
@@ -158,7 +158,7 @@ def test_graph_replays_match_eager(sc, prec, nx, launch):
 
 @pytest.mark.parametrize("prec,nxyz,shapes", [
     ("f32", (40, 40, 40), ((4, 1), (8, 1))),                        # nx <= 64: one column of 64 nodes
-    ("f16dev", (150, 12, 10), ((4, 1), (8, 1), (4, 2))),           # 16-bit, nx > 128
+    ("f16dev", (150, 12, 10), ((4, 1), (8, 1), (4, 2), (4, 4))),   # 16-bit, nx > 128: 256-wide tiles too
 ])
 def test_autotune_keeps_results(sc, prec, nxyz, shapes):
     """The autotuner sets a valid shape of those it may try, restores the time, and

@@ -301,7 +301,8 @@ def test_step_past_table_and_mach_errors(sc):
     with pytest.raises(sc.SclbmError) as ei:
         lat.set_gradient_table(np.tile(wl.simple_shear(0.05), (10, 1)), 10)
     assert ei.value.status == sc.SCLBM_EINVAL and "ghost speed" in str(ei.value)
-    # tile shapes outside (4, 1), (8, 1), (4, 2) and z-chunks below 1 are refused
+    # tile shapes outside (4, 1), (8, 1), (4, 2) and z-chunks below 1 are refused;
+    # (4, 4) exists only for the 16-bit formats
     for bad in [(2, 16, 2), (8, 16, 2), (4, 16, 3), (6, 16, 1), (4, 0, 1), (4, 16, 4)]:
         with pytest.raises(sc.SclbmError) as ei:
             lat.set_launch(*bad)
@@ -382,7 +383,9 @@ def test_c1_deviation_formats_500_steps(sc, prec):
 DEV_SHAPES = [("ghost", (150, 13, 11), (4, 5, 2)), ("periodic", (150, 13, 11), (4, 2, 2)),
               ("ghost", (70, 9, 7), (4, 100, 2)), ("periodic", (46, 6, 5), (4, 3, 2)),
               ("ghost", (45, 13, 11), (4, 5, 2)), ("ghost", (300, 6, 5), (8, 2, 1)),
-              ("periodic", (270, 6, 5), (4, 3, 2)), ("ghost", (257, 6, 5), (4, 2, 2))]
+              ("periodic", (270, 6, 5), (4, 3, 2)), ("ghost", (257, 6, 5), (4, 2, 2)),
+              ("ghost", (300, 6, 5), (4, 2, 4)), ("periodic", (270, 6, 5), (4, 3, 4)),
+              ("ghost", (150, 13, 11), (4, 5, 4)), ("periodic", (257, 6, 5), (4, 2, 4))]
 
 
 def deviation_tiles_case(sc, prec, bc, nxyz, launch, steps=20, **kw):
@@ -412,16 +415,17 @@ def deviation_tiles_case(sc, prec, bc, nxyz, launch, steps=20, **kw):
 @pytest.mark.parametrize("bc,nxyz,launch", DEV_SHAPES)
 def test_deviation_formats_tile_shapes(sc, prec, bc, nxyz, launch):
     """The 16-bit formats (both components of a population in one 32-bit word, one
-    node per lane) on 128-wide and 64 x 8 tiles against the oracle, and bit for bit
-    against 64 x 4 tiles.  nx = 150 on 128-wide tiles: a full and a 22-wide tile
-    (values cross between workgroups); nx = 70, 46: one partial tile holding whole
-    rows (periodic wrap inside it); nx = 45, 257: odd rows; ny, nz ragged against
-    the tile height and z-chunk."""
+    node per lane) on 128-wide, 256-wide and 64 x 8 tiles against the oracle, and
+    bit for bit against 64 x 4 tiles.  nx = 150 on 128-wide tiles: a full and a
+    22-wide tile (values cross between workgroups); nx = 70, 46, and 150 on
+    256-wide tiles: one partial tile holding whole rows (periodic wrap inside it);
+    nx = 300, 270, 257 on 256-wide tiles: a full tile and a 44-, 14- or 1-wide one;
+    nx = 45, 257: odd rows; ny, nz ragged against the tile height and z-chunk."""
     deviation_tiles_case(sc, prec, bc, nxyz, launch)
 
 
 @pytest.mark.parametrize("prec", ["f16dev", "bf16dev"])
-@pytest.mark.parametrize("bc,nxyz,launch", [DEV_SHAPES[0], DEV_SHAPES[6], DEV_SHAPES[7]])
+@pytest.mark.parametrize("bc,nxyz,launch", [DEV_SHAPES[0], DEV_SHAPES[7], DEV_SHAPES[9]])
 def test_deviation_formats_tile_shapes_tau3(sc, prec, bc, nxyz, launch):
     """The same at tau = 3 (Table 2; wl.TAU3), where every post-collision value
     keeps two thirds of the incoming population, so that the stored deviations
