@@ -239,7 +239,7 @@ def surrogate_study(train_steps: int = 10000, nsamp: int = 400, log=None):
         "within_5pct": bool(e["max"] <= 0.05),
         "baselines": {"sphere": {k: round(v, 5) for k, v in S.errors(np.ones_like(va.targets), va.targets).items()},
                       "maffettone_minale": {k: round(v, 5) for k, v in S.errors(mm[va.box, va.k], va.targets).items()}},
-        "roofline": {"bound": "mfma", "kernel": "inference batch (3 k_gemm_nt + k_out)",
+        "roofline": {"bound": "mfma", "kernel": "inference batch (k_forward: the four layers in one launch)",
                      "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "flops_per_batch": flops},
     }

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace sclmlp {
 
 typedef __bf16 bf16;
@@ -391,6 +393,146 @@ __global__ __launch_bounds__(256) void k_out(const bf16 *H, const bf16 *W4, cons
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Inference in one launch: the four layers for FW_M rows per workgroup, the hidden activations
+// kept in LDS.  The first layer reads the FP32 windows (16-byte aligned) and normalises them as
+// the AF32 GEMM does; every hidden product accumulates its 16-wide k-steps in the GEMM's order
+// with the same bias + ReLU epilogue, and the output layer is k_out's, so the predictions equal
+// those of the layer-by-layer path bit for bit.  Wavefront w of the 8 computes output units
+// 64 w .. 64 w + 63 of all FW_M rows (two 32 x 32 accumulator tiles) from its own weight rows,
+// loaded FW_K columns at a time.  Grid Mpad / FW_M.
+constexpr int FW_M = 32;
+constexpr int FW_K = 32;
+constexpr int FW_LDX = NIN + 8;   // 16-byte row pad: fragment reads spread over the banks
+constexpr int FW_LDH = NHID + 8;
+constexpr int FW_T = 512;         // threads
+constexpr int FW_D = 4;           // weight stages in flight per wavefront (register buffers)
+
+struct ForwardArgs {
+    const float *win;             // [n][NIN], 16-byte aligned
+    int n;
+    const float *ashift, *ascale; // input normalisation
+    const bf16 *W[3];             // hidden weights in fragment order (frag_index)
+    const float *bias[3];
+    const bf16 *W4;               // [NOUT][NHID]
+    const float *b4, *oshift, *oscale;
+    float *out;                   // [n][NOUT]
+};
+
+__global__ __launch_bounds__(FW_T) void k_forward(ForwardArgs f) {
+    __shared__ __attribute__((aligned(16))) bf16 hx[FW_M * FW_LDX];          // input, then layer 2's output
+    __shared__ __attribute__((aligned(16))) bf16 ha[FW_M * FW_LDH];          // layers 1 and 3's outputs
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * FW_M;
+
+    // input rows: (a - shift) * scale rounded to BF16, rows >= n zero
+    for (int c = tid; c < FW_M * NIN / 8; c += FW_T) {
+        const int r = c / (NIN / 8), kc = (c % (NIN / 8)) * 8;
+        const bool live = m0 + r < f.n;
+        const float4 *src = reinterpret_cast<const float4 *>(f.win + (live ? (size_t)(m0 + r) * NIN + kc : 0));
+        const float4 a0 = live ? src[0] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const float4 a1 = live ? src[1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        const float4 sa = *reinterpret_cast<const float4 *>(f.ashift + kc);
+        const float4 sb = *reinterpret_cast<const float4 *>(f.ashift + kc + 4);
+        const float4 ca = *reinterpret_cast<const float4 *>(f.ascale + kc);
+        const float4 cb = *reinterpret_cast<const float4 *>(f.ascale + kc + 4);
+        bf16x8 h;
+        h[0] = (bf16)((a0.x - sa.x) * ca.x);
+        h[1] = (bf16)((a0.y - sa.y) * ca.y);
+        h[2] = (bf16)((a0.z - sa.z) * ca.z);
+        h[3] = (bf16)((a0.w - sa.w) * ca.w);
+        h[4] = (bf16)((a1.x - sb.x) * cb.x);
+        h[5] = (bf16)((a1.y - sb.y) * cb.y);
+        h[6] = (bf16)((a1.z - sb.z) * cb.z);
+        h[7] = (bf16)((a1.w - sb.w) * cb.w);
+        if (!live) h = bf16x8{};
+        *reinterpret_cast<bf16x8 *>(hx + r * FW_LDX + kc) = h;
+    }
+
+    // one hidden layer: Hout = relu(Hin W^T + b), K = NIN or NHID.  Every weight fragment is used
+    // by one wavefront only (the one owning its output units), so each wavefront loads its own
+    // fragments, 1 KB of consecutive bytes each in the fragment-ordered copy, into a ring of FW_D
+    // register stages, FW_D - 1 stages of products ahead of their use (the loop is unrolled: buffer
+    // indices are constants); only the activations, which all wavefronts read, go through LDS.
+    auto layer = [&](auto kconst, const bf16 *Hin, int ldin, const bf16 *W, const float *bias, bf16 *Hout) {
+        constexpr int K = decltype(kconst)::value;
+        constexpr int nk = K / FW_K;
+        uint4 bq[FW_D][FW_K / 16][2];  // [stage][k-step][tile]
+        // this wavefront's tiles 2 wave, 2 wave + 1 of K / 16 fragments of 1 KB each
+        const bf16 *wtile = W + ((size_t)(2 * wave) * (K / 16) * 64 + lane) * 8;
+        auto gload = [&](int st, uint4 (&q)[FW_K / 16][2]) {
+#pragma unroll
+            for (int s = 0; s < FW_K / 16; ++s)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    q[s][j] = ld16(wtile + ((size_t)j * (K / 16) + st * (FW_K / 16) + s) * 512);
+        };
+        f32x16 acc[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[j][e] = 0.0f;
+#pragma unroll
+        for (int d = 0; d < FW_D; ++d)
+            if (d < nk) gload(d, bq[d]);
+#pragma unroll
+        for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+            for (int s = 0; s < FW_K / 16; ++s) {
+                const int kk = s * 16 + (lane >> 5) * 8;
+                const bf16x8 av = *reinterpret_cast<const bf16x8 *>(Hin + (lane & 31) * ldin + kt * FW_K + kk);
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        av, __builtin_bit_cast(bf16x8, bq[kt % FW_D][s][j]), acc[j], 0, 0, 0);
+            }
+            if (kt + FW_D < nk) gload(kt + FW_D, bq[kt % FW_D]);
+        }
+        // accumulator element 4q + e of a 32x32 tile sits at row 8q + 4 (lane / 32) + e, column lane % 32
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = wave * 64 + j * 32 + (lane & 31);
+            const float bb = bias[col];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    Hout[(8 * q + 4 * (lane >> 5) + e) * FW_LDH + col] = (bf16)fmaxf(acc[j][4 * q + e] + bb, 0.0f);
+        }
+        __syncthreads();
+    };
+    __syncthreads();
+    layer(std::integral_constant<int, NIN>{}, hx, FW_LDX, f.W[0], f.bias[0], ha);
+    layer(std::integral_constant<int, NHID>{}, ha, FW_LDH, f.W[1], f.bias[1], hx);
+    layer(std::integral_constant<int, NHID>{}, hx, FW_LDH, f.W[2], f.bias[2], ha);
+
+    // output layer (k_out's arithmetic): each wavefront FW_M / 8 rows, lane l the inputs 8 l .. 8 l + 7
+    float w[NOUT][8];
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) {
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(f.W4 + j * NHID + lane * 8);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) w[j][e] = (float)v[e];
+    }
+    for (int r = 0; r < FW_M / 8; ++r) {
+        const int rl = wave * (FW_M / 8) + r, m = m0 + rl;
+        const bf16x8 h = *reinterpret_cast<const bf16x8 *>(ha + rl * FW_LDH + lane * 8);
+        float s[NOUT] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float hv = (float)h[e];
+#pragma unroll
+            for (int j = 0; j < NOUT; ++j) s[j] = fmaf(hv, w[j][e], s[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < NOUT; ++j) s[j] = wave_sum(s[j]) + f.b4[j];
+        if (m < f.n && lane < NOUT) {
+            const float y = lane == 0 ? s[0] : (lane == 1 ? s[1] : s[2]);
+            f.out[(size_t)m * NOUT + lane] = y / f.oscale[lane] + f.oshift[lane];
+        }
+    }
+}
+
 // Sum of the per-block partials in a fixed order (thread t takes blocks t, t + 256, ...; then a
 // fixed tree): loss = sum (y - t)^2 / (3 n), db4 = sum dY.  One block of 256 threads.
 __global__ __launch_bounds__(256) void k_loss_final(const double *partial, int nblocks, int n, double *loss,
@@ -470,7 +612,16 @@ struct Seg {
     int off, rows, cols;
     bf16 *w;   // [rows][cols] copy, or null
     bf16 *wt;  // [cols][rows] copy, or null
+    bf16 *wf;  // copy in MFMA fragment order (frag_index), or null
 };
+
+// Position of W[n][k] (K = cols, a multiple of 16) in the fragment-ordered copy the one-launch
+// inference reads: [tile n / 32][k-step k / 16][lane][8], lane (n % 32) + 32 ((k % 16) / 8), so
+// that one wavefront's B fragment of a 32 x 32 x 16 product is 1 KB of consecutive bytes.
+__host__ __device__ __forceinline__ size_t frag_index(int n, int k, int K) {
+    const int lane = (n & 31) + 32 * ((k & 15) >> 3);
+    return ((size_t)((n >> 5) * (K >> 4) + (k >> 4)) * 64 + lane) * 8 + (k & 7);
+}
 struct AdamArgs {
     float *p;
     const float *g;
@@ -501,6 +652,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a) {
                 const bf16 b = (bf16)p;
                 if (q.w) q.w[o] = b;
                 if (q.wt) q.wt[(size_t)(o % q.cols) * q.rows + o / q.cols] = b;
+                if (q.wf) q.wf[frag_index(o / q.cols, o % q.cols, q.cols)] = b;
             }
         }
     }

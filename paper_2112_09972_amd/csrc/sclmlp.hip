@@ -52,7 +52,7 @@ size_t round_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
 // Byte offsets of every buffer inside the workspace for batches of up to mmax rows.
 struct Layout {
-    size_t p, g, m1, m2, norm, wb[NLAYER], wbt[NLAYER], x, xt, h[3], ht[3], dza, dzb, dzat, dzbt, dy, partial,
+    size_t p, g, m1, m2, norm, wb[NLAYER], wbt[NLAYER], wbf[3], x, xt, h[3], ht[3], dza, dzb, dzat, dzbt, dy, partial,
         loss, bad, total;
 };
 
@@ -74,6 +74,7 @@ Layout make_layout(int64_t mmax) {
     for (int l = 0; l < NLAYER; ++l) L.wb[l] = take(sizeof(bf16) * rows[l] * cols[l]);
     L.wbt[0] = L.wbt[3] = 0;
     for (int l = 1; l < 3; ++l) L.wbt[l] = take(sizeof(bf16) * NHID * NHID);
+    for (int l = 0; l < 3; ++l) L.wbf[l] = take(sizeof(bf16) * NHID * (l == 0 ? NIN : NHID));
     const size_t m = (size_t)mmax;
     L.x = take(sizeof(bf16) * m * NIN);
     L.xt = take(sizeof(bf16) * m * NIN);
@@ -115,6 +116,7 @@ struct sclmlp_ctx {
     float *out_scale() const { return at<float>(lay.norm) + 2 * NIN + NOUT; }
     bf16 *wb(int l) const { return at<bf16>(lay.wb[l]); }
     bf16 *wbt(int l) const { return at<bf16>(lay.wbt[l]); }
+    bf16 *wbf(int l) const { return at<bf16>(lay.wbf[l]); }
     bf16 *h(int l) const { return at<bf16>(lay.h[l]); }
     bf16 *ht(int l) const { return at<bf16>(lay.ht[l]); }
 };
@@ -192,10 +194,10 @@ AdamArgs adam_args(const sclmlp_ctx *c) {
     a.m = c->at<float>(c->lay.m1);
     a.v = c->at<float>(c->lay.m2);
     a.n = NPARAM;
-    a.seg[0] = Seg{OFF_W1, NHID, NIN, c->wb(0), nullptr};
-    a.seg[1] = Seg{OFF_W2, NHID, NHID, c->wb(1), c->wbt(1)};
-    a.seg[2] = Seg{OFF_W3, NHID, NHID, c->wb(2), c->wbt(2)};
-    a.seg[3] = Seg{OFF_W4, NOUT, NHID, c->wb(3), nullptr};
+    a.seg[0] = Seg{OFF_W1, NHID, NIN, c->wb(0), nullptr, c->wbf(0)};
+    a.seg[1] = Seg{OFF_W2, NHID, NHID, c->wb(1), c->wbt(1), c->wbf(1)};
+    a.seg[2] = Seg{OFF_W3, NHID, NHID, c->wb(2), c->wbt(2), c->wbf(2)};
+    a.seg[3] = Seg{OFF_W4, NOUT, NHID, c->wb(3), nullptr, nullptr};
     return a;
 }
 
@@ -321,7 +323,25 @@ sclbm_status sclmlp_predict(sclmlp_ctx *c, const float *dev_windows, int64_t n, 
     TRY(use_device(c));
     const int Mp = (int)padded_rows(n);
     if (reinterpret_cast<uintptr_t>(dev_windows) % 16 == 0) {
-        TRY(hidden_forward(c, Mp, false, dev_windows, (int)n));  // first layer reads the windows itself
+        // one launch: the four layers, activations in LDS (same results as the layer-by-layer path)
+        ForwardArgs f{};
+        f.win = dev_windows;
+        f.n = (int)n;
+        f.ashift = c->in_shift();
+        f.ascale = c->in_scale();
+        const int boff[3] = {OFF_B1, OFF_B2, OFF_B3};
+        for (int l = 0; l < 3; ++l) {
+            f.W[l] = c->wbf(l);
+            f.bias[l] = c->P() + boff[l];
+        }
+        f.W4 = c->wb(3);
+        f.b4 = c->P() + OFF_B4;
+        f.oshift = c->out_shift();
+        f.oscale = c->out_scale();
+        f.out = dev_out;
+        k_forward<<<Mp / FW_M, FW_T, 0, c->stream>>>(f);
+        HIP_LAUNCHED();
+        return SCLBM_OK;
     } else {
         k_prep<false><<<dim3(NIN / 64, Mp / 64), 256, 0, c->stream>>>(dev_windows, nullptr, nullptr, (int)n, (int)n,
                                                                         c->in_shift(), c->in_scale(),

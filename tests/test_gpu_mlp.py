@@ -109,6 +109,30 @@ def test_predict_normalisation(env):
     assert err <= 1e-2
 
 
+def test_predict_one_launch_equals_layer_path(env):
+    """Inference of 16-byte-aligned windows runs the four layers in one launch
+    (k_forward, activations in LDS); any other alignment takes the layer-by-layer
+    path (input kernel, three GEMMs, output kernel).  Both give the same bits, on a
+    ragged batch and on one that fills the padded rows, with a non-trivial input
+    and output normalisation."""
+    torch, mlp = env
+    net, p = setup_net(torch, mlp, 13, max_batch=1024)
+    rng = np.random.default_rng(21)
+    shift = rng.standard_normal(576).astype(np.float32) * 0.1
+    scale = (1.0 + rng.random(576)).astype(np.float32)
+    net.set_normalization(shift, scale, np.array([1.0, 0.9, 0.8], np.float32), np.array([10.0, 20.0, 30.0], np.float32))
+    for n in (1000, 77, 1024):
+        w = (rng.standard_normal((n, 576)) * 0.5).astype(np.float32)
+        aligned = torch.from_numpy(w).cuda()
+        buf = torch.zeros(n * 576 + 1, dtype=torch.float32, device="cuda")
+        buf[1:].copy_(aligned.reshape(-1))
+        shifted = buf[1:].view(n, 576)
+        assert aligned.data_ptr() % 16 == 0 and shifted.data_ptr() % 16 != 0
+        a = net.predict(aligned).cpu().numpy()
+        b = net.predict(shifted).cpu().numpy()
+        assert np.array_equal(a, b), (n, np.abs(a - b).max())
+
+
 def check_grads(g_gpu, g_ref, rel, label):
     for name, a, b in zip(["W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4"], ref.unflatten(g_gpu), ref.unflatten(g_ref)):
         e = np.linalg.norm(a - b) / np.linalg.norm(b)
