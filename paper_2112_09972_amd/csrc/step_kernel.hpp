@@ -552,26 +552,52 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         // consecutive elements (whole cache lines).  A tile that does not hold whole
         // rows also writes the one value that leaves it across each edge.
         if (valid) {
+            // FP32 storage reads all ten values per component first, so that the LDS
+            // reads overlap instead of each store waiting for its own read (FP64
+            // storage has no registers left for them)
+            constexpr bool BATCH = PREFETCH;
+            B wq[2][NXD];
+            if constexpr (BATCH) {
 #pragma unroll
-            for (int jx = 0; jx < NXD; ++jx) {
-                const int i = jx < 2 ? jx + 1 : jx + 5;
-                const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
-                int yd = y + cy, zd = zc + cz;
-                bool out = false;
+                for (int jx = 0; jx < NXD; ++jx) {
+                    const int cx = cx_of(jx < 2 ? jx + 1 : jx + 5);
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) wq[s][jx] = xq[s][jx][ly][lx + 1 - cx];
+                }
+            }
+            // destination row of direction i and whether it lies outside the box (ghost mode)
+            auto dest_row = [&](int i, bool &out) -> uint32_t {
+                int yd = y + cy_of(i), zd = zc + cz_of(i);
+                out = false;
                 if (GHOST) {
                     out = yd < 0 || yd >= ny || zd < 0 || zd >= nz;
                 } else {
                     yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
                     zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
                 }
-                const uint32_t row = (uint32_t(zd) * uint32_t(ny) + uint32_t(yd)) * qnx + uint32_t(i) * uint32_t(nx);
+                return (uint32_t(zd) * uint32_t(ny) + uint32_t(yd)) * qnx + uint32_t(i) * uint32_t(nx);
+            };
+#pragma unroll
+            for (int jx = 0; jx < NXD; ++jx) {
+                const int i = jx < 2 ? jx + 1 : jx + 5;
+                const int cx = cx_of(i);
+                bool out;
+                const uint32_t row = dest_row(i, out);
                 bool ok = !out;
                 if (cx > 0 && lx == 0) ok = ok && (GHOST ? left_face : span);
                 if (cx < 0 && lx == tw - 1) ok = ok && (GHOST ? right_face : span);
 #pragma unroll
                 for (int s = 0; s < 2; ++s)
-                    Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0, xq[s][jx][ly][lx + 1 - cx]);
-                if (!span) {
+                    Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0,
+                                         BATCH ? wq[s][jx] : xq[s][jx][ly][lx + 1 - cx]);
+            }
+            if (!span) {
+#pragma unroll
+                for (int jx = 0; jx < NXD; ++jx) {
+                    const int i = jx < 2 ? jx + 1 : jx + 5;
+                    const int cx = cx_of(i);
+                    bool out;
+                    const uint32_t row = dest_row(i, out);
                     const bool edge = cx > 0 ? lx == tw - 1 : lx == 0;
                     int xd = x + cx;
                     bool go = edge && !out;
