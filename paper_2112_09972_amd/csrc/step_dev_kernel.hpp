@@ -167,7 +167,7 @@ __device__ __forceinline__ float2 dev_ref(float rho) {
 
 // Bracket 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u^2 of a ghost population (Sec. 2 Eq. 8),
 // its velocity A (x_g - x_c) from the displacement (dx, dy, dz); c = (cx, cy, cz).
-__device__ __forceinline__ float ghost_bracket(const float (&A)[9], float dx, float dy, float dz, int cx, int cy,
+__device__ __forceinline__ float ghost_bracket(const float *A, float dx, float dy, float dz, int cx, int cy,
                                                int cz) {
     const float gx = __builtin_fmaf(A[0], dx, __builtin_fmaf(A[1], dy, A[2] * dz));
     const float gy = __builtin_fmaf(A[3], dx, __builtin_fmaf(A[4], dy, A[5] * dz));
@@ -235,15 +235,23 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
     const int64_t n = *a.clk_in;
     if (lin == 0 && tid == 0) *a.clk_out = n + 1;
 
-    const float rhob[2] = {float(a.rho_b[0]), float(a.rho_b[1])};
-    float Am[9];
+    // Values that are the same in every lane are taken into scalar registers
+    // (readfirstlane): held in vector registers through the march they pushed the
+    // kernel past its 128 registers into scratch, and the compiler then waited for
+    // all outstanding memory operations several times per plane.
+    auto uni = [](float v) { return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v))); };
+    const float rhob[2] = {uni(float(a.rho_b[0])), uni(float(a.rho_b[1]))};
+    // velocity gradient of step n (row-major) and box centre, for the ghost nodes
+    float gsc[12];
     if (GHOST) {
         const double *Arow = a.atab + ((int64_t)box * a.table_len + (n - a.tab_first[box])) * 9;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) Am[q] = float(Arow[q]);
+        for (int q = 0; q < 9; ++q) gsc[q] = uni(float(Arow[q]));
+#pragma unroll
+        for (int q = 0; q < 3; ++q) gsc[9 + q] = uni(float(a.xc[q]));
     }
-    const float om0 = float(a.omega[0]), om1 = float(a.omega[1]);
-    const float gt0 = float(a.g) * float(a.tau[0]), gt1 = float(a.g) * float(a.tau[1]);
+    const float om0 = uni(float(a.omega[0])), om1 = uni(float(a.omega[1]));
+    const float gt0 = uni(float(a.g) * float(a.tau[0])), gt1 = uni(float(a.g) * float(a.tau[1]));
 
     static_assert(2 * (TXW + 2) + 2 * TY <= TXW * TY, "one ring node per thread");
     const int ringN = 2 * (tw + 2) + 2 * th;
@@ -430,12 +438,18 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
         if (GHOST && y < ny) {
             // Populations streaming in from ghost nodes, which hold
             // g_eq(rho_b, A (x_g - x_c)) (values per weight: rho_b times the bracket).
+            // The lane's coordinates pass through an empty asm first, so that what this
+            // code derives from them is computed here each plane instead of being
+            // hoisted out of the march and held in registers (or scratch).
+            int bl = lane, bx_ = x, by_ = y, blx = lx, bly = ly;
+            asm volatile("" : "+v"(bl), "+v"(bx_), "+v"(by_), "+v"(blx), "+v"(bly));
+            const float *A = gsc, *xcf = gsc + 9;
             // (a) Ghosts beside this row at x = -1 and x = nx, into the edge columns of
             // the x exchange: lanes 0-9 of the first wavefront the left side, lanes
             // 16-25 of the last the right, lane 2m + s computing component s of
             // direction m and lane 2m writing the word.
-            const int side = lane < 16 ? 0 : 1;
-            const int q = lane - 16 * side;
+            const int side = bl < 16 ? 0 : 1;
+            const int q = bl - 16 * side;
             if (q < 10 && (side ? (right_face && wv == nw - 1) : (left_face && wv == 0))) {
                 const int sgn = side ? -1 : 1;  // c_x of the incoming directions
                 const int m = q >> 1, s = q & 1;
@@ -445,28 +459,27 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
                 const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
                                         : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
                 const int fx = side ? nx - 1 : 0;  // the receiving face node's x
-                const float br = ghost_bracket(Am, float(fx - sgn) - float(a.xc[0]), float(y) - float(a.xc[1]),
-                                               float(zc) - float(a.xc[2]), sgn, cyv, czv);
+                const float br = ghost_bracket(A, float(fx - sgn) - xcf[0], float(by_) - xcf[1], float(zc) - xcf[2], sgn,
+                                               cyv, czv);
                 // the receiver (fx, y + c_y, z + c_z) lies in the LDS window
-                const float4 qr = rmq[sl(czv)][ly + 1 + cyv][fx - x0 + 1];
+                const float4 qr = rmq[sl(czv)][bly + 1 + cyv][fx - x0 + 1];
                 const uint32_t bits =
                     s ? dev_enc<P>(rhob[1] * br, qr.z, qr.w) : dev_enc<P>(rhob[0] * br, qr.x, qr.y);
                 const uint32_t other = uint32_t(__shfl_xor(int(bits), 1, 64));  // the pair lane's component
-                if (s == 0) xq[xslot_of(idx)][ly][side ? tw + 1 : 0] = bits | (other << 16);
+                if (s == 0) xq[xslot_of(idx)][bly][side ? tw + 1 : 0] = bits | (other << 16);
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
             // the directions whose source lies outside the box in y or z, edges and
             // corners included, both components as one word.
             if (valid && (ylo || yhi || zlo || zhi)) {
-                const float dx0 = float(x) - float(a.xc[0]), dy0 = float(y) - float(a.xc[1]),
-                            dz0 = float(zc) - float(a.xc[2]);
-                const float4 qr = rmq[sl(0)][ly + 1][lx + 1];
+                const float dx0 = float(bx_) - xcf[0], dy0 = float(by_) - xcf[1], dz0 = float(zc) - xcf[2];
+                const float4 qr = rmq[sl(0)][bly + 1][blx + 1];
 #pragma nounroll
                 for (int i = 1; i < Q; ++i) {
                     const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
                     const bool from_yz = (cy > 0 && ylo) || (cy < 0 && yhi) || (cz > 0 && zlo) || (cz < 0 && zhi);
                     if (!from_yz) continue;
-                    const float br = ghost_bracket(Am, dx0 - float(cx), dy0 - float(cy), dz0 - float(cz), cx, cy, cz);
+                    const float br = ghost_bracket(A, dx0 - float(cx), dy0 - float(cy), dz0 - float(cz), cx, cy, cz);
                     const uint32_t w = uint32_t(dev_enc<P>(rhob[0] * br, qr.x, qr.y)) |
                                        (uint32_t(dev_enc<P>(rhob[1] * br, qr.z, qr.w)) << 16);
                     __builtin_amdgcn_raw_buffer_store_b32(w, rd, vo + uint32_t(i) * plane_bytes, 0, kStoreNT);
