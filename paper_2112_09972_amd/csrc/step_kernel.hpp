@@ -183,6 +183,8 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     // that nothing waits for them during the collision) are loaded while the
     // current one collides.  FP64 windows leave no registers for a third plane.
     constexpr bool PREFETCH = sizeof(S) < 8;
+    // the x-exchange values read from LDS together before their stores (FP32 storage)
+    constexpr bool BATCH = PREFETCH;
     static_assert(!Prec<P>::DEV, "the 16-bit deviation formats run k_step_dev");
     // density window: the planes zc - 1, zc, zc + 1 of the collision and one more
     constexpr int NSLOT = 4;
@@ -551,19 +553,15 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         // pushed from x - c_x, so that every store of a wavefront covers 64 aligned
         // consecutive elements (whole cache lines).  A tile that does not hold whole
         // rows also writes the one value that leaves it across each edge.
-        if (valid) {
-            // FP32 storage reads all ten values per component first, so that the LDS
-            // reads overlap instead of each store waiting for its own read (FP64
-            // storage has no registers left for them)
-            constexpr bool BATCH = PREFETCH;
+        if (valid && BATCH) {
+            // FP32 storage: all ten values per component first, so that the LDS reads
+            // overlap instead of each store waiting for its own read
             B wq[2][NXD];
-            if constexpr (BATCH) {
 #pragma unroll
-                for (int jx = 0; jx < NXD; ++jx) {
-                    const int cx = cx_of(jx < 2 ? jx + 1 : jx + 5);
+            for (int jx = 0; jx < NXD; ++jx) {
+                const int cx = cx_of(jx < 2 ? jx + 1 : jx + 5);
 #pragma unroll
-                    for (int s = 0; s < 2; ++s) wq[s][jx] = xq[s][jx][ly][lx + 1 - cx];
-                }
+                for (int s = 0; s < 2; ++s) wq[s][jx] = xq[s][jx][ly][lx + 1 - cx];
             }
             // destination row of direction i and whether it lies outside the box (ghost mode)
             auto dest_row = [&](int i, bool &out) -> uint32_t {
@@ -587,10 +585,11 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 if (cx > 0 && lx == 0) ok = ok && (GHOST ? left_face : span);
                 if (cx < 0 && lx == tw - 1) ok = ok && (GHOST ? right_face : span);
 #pragma unroll
-                for (int s = 0; s < 2; ++s)
-                    Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0,
-                                         BATCH ? wq[s][jx] : xq[s][jx][ly][lx + 1 - cx]);
+                for (int s = 0; s < 2; ++s) Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0, wq[s][jx]);
             }
+            // a tile that does not hold whole rows also writes the value leaving it
+            // across each edge, in a loop of its own so that no branch separates the
+            // reads above from their stores
             if (!span) {
 #pragma unroll
                 for (int jx = 0; jx < NXD; ++jx) {
@@ -598,6 +597,40 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                     const int cx = cx_of(i);
                     bool out;
                     const uint32_t row = dest_row(i, out);
+                    const bool edge = cx > 0 ? lx == tw - 1 : lx == 0;
+                    int xd = x + cx;
+                    bool go = edge && !out;
+                    if (GHOST) go = go && (cx > 0 ? !right_face : !left_face);
+                    else xd = xd < 0 ? xd + nx : (xd >= nx ? xd - nx : xd);
+                    if (go) {
+#pragma unroll
+                        for (int s = 0; s < 2; ++s)
+                            Prec<P>::bstore_bits(rd[s], (row + uint32_t(xd)) * EB, 0, xq[s][jx][ly][lx + 1]);
+                    }
+                }
+            }
+        } else if (valid) {
+            // FP64 storage (no registers left for the values): one read per store
+#pragma unroll
+            for (int jx = 0; jx < NXD; ++jx) {
+                const int i = jx < 2 ? jx + 1 : jx + 5;
+                const int cx = cx_of(i), cy = cy_of(i), cz = cz_of(i);
+                int yd = y + cy, zd = zc + cz;
+                bool out = false;
+                if (GHOST) {
+                    out = yd < 0 || yd >= ny || zd < 0 || zd >= nz;
+                } else {
+                    yd = yd < 0 ? yd + ny : (yd >= ny ? yd - ny : yd);
+                    zd = zd < 0 ? zd + nz : (zd >= nz ? zd - nz : zd);
+                }
+                const uint32_t row = (uint32_t(zd) * uint32_t(ny) + uint32_t(yd)) * qnx + uint32_t(i) * uint32_t(nx);
+                bool ok = !out;
+                if (cx > 0 && lx == 0) ok = ok && (GHOST ? left_face : span);
+                if (cx < 0 && lx == tw - 1) ok = ok && (GHOST ? right_face : span);
+#pragma unroll
+                for (int s = 0; s < 2; ++s)
+                    Prec<P>::bstore_bits(rd[s], ok ? (row + uint32_t(x)) * EB : kOOB, 0, xq[s][jx][ly][lx + 1 - cx]);
+                if (!span) {
                     const bool edge = cx > 0 ? lx == tw - 1 : lx == 0;
                     int xd = x + cx;
                     bool go = edge && !out;
