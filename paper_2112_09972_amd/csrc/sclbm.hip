@@ -218,7 +218,10 @@ void default_tile(const sclbm_config &c, int &ty, int &wx) {
     // full or more than 160 nodes long (no ring columns loaded from a neighbouring
     // tile of the row: each such node costs 19 cache lines for 76 bytes)
     const int tail256 = c.nx % 256;
-    if (valid_tile(c, 4, 4) && c.nx > 128 && (tail256 == 0 || tail256 > 160)) wx = 4;
+    if (valid_tile(c, 4, 4) && c.nx > 128 && (tail256 == 0 || tail256 > 160)) {
+        ty = 4;
+        wx = 4;
+    }
 }
 
 // z-chunk of a launch.  FP64 and FP32: two waves per SIMD are resident (the

@@ -121,6 +121,7 @@ def test_empty_droplet():
     (32, 1, 0, (8, 2, 1)),
     (256, 1, 2, (4, 32, 4)),   # 16-bit formats: 256-wide tiles, four waves per SIMD, chunks <= 32 planes
     (200, 1, 3, (4, 20, 4)),   # last 256-wide tile more than 160 nodes
+    (192, 1, 2, (4, 12, 4)),   # a 256-wide tile holds the row: four rows, even where the 128-wide rules take 64 x 8
     (160, 1, 2, (8, 20, 1)),   # not: 128-wide rules
     (150, 1, 2, (8, 19, 1)),
     (128, 1, 2, (4, 8, 2)),
