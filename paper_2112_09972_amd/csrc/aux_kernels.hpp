@@ -215,16 +215,49 @@ __device__ __forceinline__ void block_reduce_store(double (&v)[K], double *out /
 template <int P>
 __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::S *f, const __half *ref, BoxGeom g,
                                                         int b0, double *partial) {
+    using S = typename Prec<P>::S;
+    using R = typename Prec<P>::R;
     const int box = b0 + blockIdx.y;
     f += (int64_t)box * 2 * Q * g.nnode;
     if (Prec<P>::DEV) ref += (int64_t)box * 2 * g.nnode;
     double v[NSTAT];
 #pragma unroll
     for (int c = 0; c < NSTAT; ++c) v[c] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.nnode; k += stride) {
+    // Thread t takes nodes k = t, t + stride, ... (k = (z ny + y) nx + x), carrying (x, y, z) from
+    // one to the next, so that the loop does no integer division; a box holds fewer than 2^31 nodes.
+    const uint32_t nn = uint32_t(g.nnode), nx = uint32_t(g.nx), ny = uint32_t(g.ny);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t x = k % nx, y = (k / nx) % ny, z = k / nx / ny;
+    const uint32_t sx = stride % nx, sy = (stride / nx) % ny, sz = stride / nx / ny;
+    // FP64 and FP32 storage: raw buffer loads, one byte offset per node and a uniform one per
+    // direction (the 16-bit formats take the decoding loads of node_moments)
+    constexpr uint32_t EB = sizeof(S);
+    const uint32_t comp_bytes = uint32_t(Q) * nn * EB, plane_bytes = nx * EB;
+    const rsrc_t rs[2] = {make_rsrc(f, comp_bytes), make_rsrc(f + (int64_t)Q * g.nnode, comp_bytes)};
+    for (; k < nn; k += stride) {
         double rho[2], j[2][3];
-        node_moments<P>(f, ref, g, k, rho, j);
+        if constexpr (Prec<P>::DEV) {
+            node_moments<P>(f, ref, g, k, rho, j);
+        } else {
+            const uint32_t vo = ((z * ny + y) * uint32_t(Q) * nx + x) * EB;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const double w = double(Prec<P>::bload(rs[s], vo, uint32_t(i) * plane_bytes, R(0)));
+                    r += w;
+                    if (cx_of(i)) jx += double(cx_of(i)) * w;
+                    if (cy_of(i)) jy += double(cy_of(i)) * w;
+                    if (cz_of(i)) jz += double(cz_of(i)) * w;
+                }
+                rho[s] = r;
+                j[s][0] = jx;
+                j[s][1] = jy;
+                j[s][2] = jz;
+            }
+        }
         v[0] += rho[0];
         v[1] += rho[1];
         v[2] += j[0][0] + j[1][0];
@@ -232,9 +265,7 @@ __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::
         v[4] += j[0][2] + j[1][2];
         if (!(rho[0] > 0.0) || !(rho[1] > 0.0) || !isfinite(rho[0]) || !isfinite(rho[1])) v[15] += 1.0;
         if (rho[0] > rho[1]) {
-            int x, y, z;
-            node_xyz(g, k, x, y, z);
-            const double dx = x - g.xc[0], dy = y - g.xc[1], dz = z - g.xc[2];
+            const double dx = double(x) - g.xc[0], dy = double(y) - g.xc[1], dz = double(z) - g.xc[2];
             v[5] += 1.0;
             v[6] += dx;
             v[7] += dy;
@@ -246,6 +277,14 @@ __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::
             v[13] += dy * dz;
             v[14] += dz * dz;
         }
+        // the next node's coordinates: add (sx, sy, sz) with carries (sx < nx, sy < ny)
+        x += sx;
+        const uint32_t carry_x = x >= nx ? 1u : 0u;
+        x -= carry_x * nx;
+        y += sy + carry_x;
+        const uint32_t carry_y = y >= ny ? 1u : 0u;
+        y -= carry_y * ny;
+        z += sz + carry_y;
     }
     block_reduce_store<NSTAT>(v, partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * NSTAT);
 }
