@@ -453,3 +453,39 @@ def test_deviation_formats_stationary_and_checkpoint(sc, prec):
     lat2.load(ck)
     lat2.step(30)
     assert np.array_equal(lat2.save(), end)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16dev"])
+def test_moments_where_threads_visit_several_nodes(sc, prec):
+    """The statistics reduction gives thread t the nodes t, t + stride, ... and
+    carries their coordinates from one node to the next.  On a 100 x 90 x 80 box
+    the stride (1024 workgroups of 256 threads) advances 44 in x, 11 in y and 29
+    in z, with carries in x and y; the indicator moments of an off-centre droplet
+    (integer and half-integer sums, exact in FP64) must equal the same sums over
+    the density fields the library returns, and the masses their sums."""
+    import torch
+    nx, ny, nz = 100, 90, 80
+    A = np.array([[0.0, 0.0, 0.002], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    lat = sc.Lattice(nx, ny, nz, bc="ghost", prec=prec, table_len=8, g_ab=wl.G_AB, rho_b=wl.ghost_densities(12.0))
+    lat.init_droplet((40.3, 47.1, 33.8), 12.0, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, A.ravel())
+    lat.set_gradient(A.ravel())
+    lat.step(5)
+    ra, rb, _ = (t.cpu().numpy().astype(np.float64) for t in lat.fields())
+    out = torch.zeros(10, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()  # the fill (torch's stream) before the library's stream writes
+    lat.droplet_moments(out)
+    lat.synchronize()
+    got = out.cpu().numpy()
+    # fields are [z][y][x]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ind = ra > rb
+    d = [x[ind] - lat.xc[0], y[ind] - lat.xc[1], z[ind] - lat.xc[2]]
+    want = [ind.sum(), d[0].sum(), d[1].sum(), d[2].sum(), (d[0] * d[0]).sum(), (d[0] * d[1]).sum(),
+            (d[0] * d[2]).sum(), (d[1] * d[1]).sum(), (d[1] * d[2]).sum(), (d[2] * d[2]).sum()]
+    assert want[0] > 1000
+    assert np.array_equal(got, np.array(want, dtype=np.float64)), (got, want)
+    # masses: the same FP64 sums in another order; the 16-bit formats' density fields and
+    # totals decode the populations in FP32 along different routes (6e-8 of each value)
+    tol = 1e-7 if prec.endswith("dev") else 1e-12
+    m, _ = lat.totals()
+    assert abs(m[0] - ra.sum()) <= tol * ra.sum() and abs(m[1] - rb.sum()) <= tol * rb.sum()
