@@ -441,15 +441,15 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
             // The lane's coordinates pass through an empty asm first, so that what this
             // code derives from them is computed here each plane instead of being
             // hoisted out of the march and held in registers (or scratch).
-            int bl = lane, bx_ = x, by_ = y, blx = lx, bly = ly;
-            asm volatile("" : "+v"(bl), "+v"(bx_), "+v"(by_), "+v"(blx), "+v"(bly));
+            int lane_b = lane, x_b = x, y_b = y, lx_b = lx, ly_b = ly;
+            asm volatile("" : "+v"(lane_b), "+v"(x_b), "+v"(y_b), "+v"(lx_b), "+v"(ly_b));
             const float *A = gsc, *xcf = gsc + 9;
             // (a) Ghosts beside this row at x = -1 and x = nx, into the edge columns of
             // the x exchange: lanes 0-9 of the first wavefront the left side, lanes
             // 16-25 of the last the right, lane 2m + s computing component s of
             // direction m and lane 2m writing the word.
-            const int side = bl < 16 ? 0 : 1;
-            const int q = bl - 16 * side;
+            const int side = lane_b < 16 ? 0 : 1;
+            const int q = lane_b - 16 * side;
             if (q < 10 && (side ? (right_face && wv == nw - 1) : (left_face && wv == 0))) {
                 const int sgn = side ? -1 : 1;  // c_x of the incoming directions
                 const int m = q >> 1, s = q & 1;
@@ -459,21 +459,21 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
                 const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
                                         : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
                 const int fx = side ? nx - 1 : 0;  // the receiving face node's x
-                const float br = ghost_bracket(A, float(fx - sgn) - xcf[0], float(by_) - xcf[1], float(zc) - xcf[2], sgn,
+                const float br = ghost_bracket(A, float(fx - sgn) - xcf[0], float(y_b) - xcf[1], float(zc) - xcf[2], sgn,
                                                cyv, czv);
                 // the receiver (fx, y + c_y, z + c_z) lies in the LDS window
-                const float4 qr = rmq[sl(czv)][bly + 1 + cyv][fx - x0 + 1];
+                const float4 qr = rmq[sl(czv)][ly_b + 1 + cyv][fx - x0 + 1];
                 const uint32_t bits =
                     s ? dev_enc<P>(rhob[1] * br, qr.z, qr.w) : dev_enc<P>(rhob[0] * br, qr.x, qr.y);
                 const uint32_t other = uint32_t(__shfl_xor(int(bits), 1, 64));  // the pair lane's component
-                if (s == 0) xq[xslot_of(idx)][bly][side ? tw + 1 : 0] = bits | (other << 16);
+                if (s == 0) xq[xslot_of(idx)][ly_b][side ? tw + 1 : 0] = bits | (other << 16);
             }
             // (b) y and z faces (whole rows and planes): each boundary lane writes
             // the directions whose source lies outside the box in y or z, edges and
             // corners included, both components as one word.
             if (valid && (ylo || yhi || zlo || zhi)) {
-                const float dx0 = float(bx_) - xcf[0], dy0 = float(by_) - xcf[1], dz0 = float(zc) - xcf[2];
-                const float4 qr = rmq[sl(0)][bly + 1][blx + 1];
+                const float dx0 = float(x_b) - xcf[0], dy0 = float(y_b) - xcf[1], dz0 = float(zc) - xcf[2];
+                const float4 qr = rmq[sl(0)][ly_b + 1][lx_b + 1];
 #pragma nounroll
                 for (int i = 1; i < Q; ++i) {
                     const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
