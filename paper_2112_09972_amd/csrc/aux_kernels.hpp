@@ -235,29 +235,8 @@ __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::
     constexpr uint32_t EB = sizeof(S);
     const uint32_t comp_bytes = uint32_t(Q) * nn * EB, plane_bytes = nx * EB;
     const rsrc_t rs[2] = {make_rsrc(f, comp_bytes), make_rsrc(f + (int64_t)Q * g.nnode, comp_bytes)};
-    for (; k < nn; k += stride) {
-        double rho[2], j[2][3];
-        if constexpr (Prec<P>::DEV) {
-            node_moments<P>(f, ref, g, k, rho, j);
-        } else {
-            const uint32_t vo = ((z * ny + y) * uint32_t(Q) * nx + x) * EB;
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    const double w = double(Prec<P>::bload(rs[s], vo, uint32_t(i) * plane_bytes, R(0)));
-                    r += w;
-                    if (cx_of(i)) jx += double(cx_of(i)) * w;
-                    if (cy_of(i)) jy += double(cy_of(i)) * w;
-                    if (cz_of(i)) jz += double(cz_of(i)) * w;
-                }
-                rho[s] = r;
-                j[s][0] = jx;
-                j[s][1] = jy;
-                j[s][2] = jz;
-            }
-        }
+    // the node's contributions, in a fixed order (one node after the other)
+    auto accumulate = [&](const double (&rho)[2], const double (&j)[2][3], uint32_t xx, uint32_t yy, uint32_t zz) {
         v[0] += rho[0];
         v[1] += rho[1];
         v[2] += j[0][0] + j[1][0];
@@ -265,7 +244,7 @@ __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::
         v[4] += j[0][2] + j[1][2];
         if (!(rho[0] > 0.0) || !(rho[1] > 0.0) || !isfinite(rho[0]) || !isfinite(rho[1])) v[15] += 1.0;
         if (rho[0] > rho[1]) {
-            const double dx = double(x) - g.xc[0], dy = double(y) - g.xc[1], dz = double(z) - g.xc[2];
+            const double dx = double(xx) - g.xc[0], dy = double(yy) - g.xc[1], dz = double(zz) - g.xc[2];
             v[5] += 1.0;
             v[6] += dx;
             v[7] += dy;
@@ -277,14 +256,83 @@ __global__ __launch_bounds__(NRED_THREADS) void k_stats(const typename Prec<P>::
             v[13] += dy * dz;
             v[14] += dz * dz;
         }
-        // the next node's coordinates: add (sx, sy, sz) with carries (sx < nx, sy < ny)
-        x += sx;
-        const uint32_t carry_x = x >= nx ? 1u : 0u;
-        x -= carry_x * nx;
-        y += sy + carry_x;
-        const uint32_t carry_y = y >= ny ? 1u : 0u;
-        y -= carry_y * ny;
-        z += sz + carry_y;
+    };
+    // the next node's coordinates: add (sx, sy, sz) with carries (sx < nx, sy < ny)
+    auto advance = [&](uint32_t &xx, uint32_t &yy, uint32_t &zz) {
+        xx += sx;
+        const uint32_t carry_x = xx >= nx ? 1u : 0u;
+        xx -= carry_x * nx;
+        yy += sy + carry_x;
+        const uint32_t carry_y = yy >= ny ? 1u : 0u;
+        yy -= carry_y * ny;
+        zz += sz + carry_y;
+    };
+    // density and momentum of a node from its 2 x 19 populations, summed in FP64
+    auto moments = [&](const auto &w, double (&rho)[2], double (&j)[2][3]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double wi = double(w[s][i]);
+                r += wi;
+                if (cx_of(i)) jx += double(cx_of(i)) * wi;
+                if (cy_of(i)) jy += double(cy_of(i)) * wi;
+                if (cz_of(i)) jz += double(cz_of(i)) * wi;
+            }
+            rho[s] = r;
+            j[s][0] = jx;
+            j[s][1] = jy;
+            j[s][2] = jz;
+        }
+    };
+    auto node_vo = [&](uint32_t xx, uint32_t yy, uint32_t zz) { return ((zz * ny + yy) * uint32_t(Q) * nx + xx) * EB; };
+    if constexpr (Prec<P>::DEV) {
+        for (; k < nn; k += stride) {
+            double rho[2], j[2][3];
+            node_moments<P>(f, ref, g, k, rho, j);
+            accumulate(rho, j, x, y, z);
+            advance(x, y, z);
+        }
+    } else if constexpr (sizeof(S) == 4) {
+        // FP32 storage: the loads of node k + stride go out while node k is summed
+        float wn[2][Q];
+        auto load = [&](uint32_t vo) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) wn[s][i] = Prec<P>::bload(rs[s], vo, uint32_t(i) * plane_bytes, R(0));
+        };
+        if (k < nn) load(node_vo(x, y, z));
+        for (; k < nn; k += stride) {
+            float w[2][Q];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) w[s][i] = wn[s][i];
+            uint32_t xn = x, yn = y, zn = z;
+            advance(xn, yn, zn);
+            if (k + stride < nn) load(node_vo(xn, yn, zn));
+            double rho[2], j[2][3];
+            moments(w, rho, j);
+            accumulate(rho, j, x, y, z);
+            x = xn;
+            y = yn;
+            z = zn;
+        }
+    } else {
+        for (; k < nn; k += stride) {
+            S w[2][Q];
+            const uint32_t vo = node_vo(x, y, z);
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) w[s][i] = Prec<P>::bload(rs[s], vo, uint32_t(i) * plane_bytes, R(0));
+            double rho[2], j[2][3];
+            moments(w, rho, j);
+            accumulate(rho, j, x, y, z);
+            advance(x, y, z);
+        }
     }
     block_reduce_store<NSTAT>(v, partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * NSTAT);
 }
