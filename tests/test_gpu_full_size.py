@@ -1,0 +1,89 @@
+"""Parity at the benchmark's full sizes and launch shapes (through the C ABI).
+
+The 128^3 FP32 box of the headline run has its own full-size test in
+test_gpu_parity.py; here the other two configurations the benchmark and the
+precision study time: 64 boxes of 64^3 in one launch per step (FP32, each box
+with its own OU drive, the launch the autotuner picks for them), compared with
+the FP64 oracle on every node of three boxes; and the 256^3 box in the 16-bit
+deviation formats at their default launch, compared with one oracle run on
+every node.  Tolerances: 1e-5 for FP32 storage as everywhere; the deviation
+formats' bound of the 500-step runs (2e-3 / 2e-2), which a 10-step run stays
+far inside.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_09972_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_09972_amd as sc
+    sc.load()
+    return sc
+
+
+def max_rel(lat, o, box=0):
+    ra, rb, _ = (t.cpu().numpy() for t in lat.fields(box=box))
+    oa, ob, _ = o.fields()
+    return max(np.max(np.abs(ra - oa) / np.abs(oa)), np.max(np.abs(rb - ob) / np.abs(ob)))
+
+
+def test_ensemble_64_boxes_of_64_cubed(sc):
+    """64 boxes of 64^3, tiles of 64 x 8 with 64-plane chunks (the benchmark's
+    ensemble launch), 40 steps of their OU drives: boxes 0, 31 and 63 (the
+    weakest, a middle and the strongest drive) match the oracle on every node."""
+    steps = 40
+    case = wl.case_c4(nsteps=steps + 1)
+    n, nbox, R = case.n, case.nbox, case.radius
+    lat = sc.Lattice(n, n, n, nbox=nbox, bc="ghost", prec="f32", table_len=steps, g_ab=wl.G_AB, rho_b=case.rho_b,
+                     mach_max=wl.MACH_MAX)
+    lat.set_launch(8, 64, 1)
+    for b in range(nbox):
+        lat.init_droplet(lat.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, case.tables[b][0], box=b)
+        lat.set_gradient_table(case.tables[b][:steps], 0, box=b)
+    lat.step(steps)
+    for b in (0, 31, 63):
+        o = oracle.Oracle(n, n, n, periodic=False, g=wl.G_AB, rho_b=case.rho_b)
+        o.init_droplet(o.xc, R, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, case.tables[b][0])
+        o.run(steps, case.tables[b][:steps])
+        err = max_rel(lat, o, box=b)
+        print("64 x 64^3 box %d: max rel. density error %.2e" % (b, err))
+        assert err <= 1e-5, (b, err)
+
+
+@pytest.fixture(scope="module")
+def oracle_256():
+    """One FP64 oracle run of the 256^3 box (R = 32, OU seed 3), 10 steps."""
+    steps = 10
+    case = wl.case_c3(nsteps=steps + 1)
+    o = oracle.Oracle(256, 256, 256, periodic=False, g=wl.G_AB, rho_b=case.rho_b)
+    o.init_droplet(o.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, case.tables[0][0])
+    o.run(steps, case.tables[0][:steps])
+    ra, rb, _ = o.fields()
+    del o
+    return case, steps, ra, rb
+
+
+@pytest.mark.parametrize("prec,tol", [("f16dev", 2e-3), ("bf16dev", 2e-2)])
+def test_256_cubed_deviation_formats(sc, oracle_256, prec, tol):
+    """The 256^3 box at the default launch of the 16-bit formats (256 x 4 tiles,
+    32-plane chunks) after 10 steps of its OU drive, on every node."""
+    case, steps, oa, ob = oracle_256
+    lat = sc.Lattice(256, 256, 256, bc="ghost", prec=prec, table_len=steps, g_ab=wl.G_AB, rho_b=case.rho_b,
+                     mach_max=wl.MACH_MAX)
+    assert lat.get_launch() == (4, 32, 4)
+    lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, case.tables[0][0])
+    lat.set_gradient_table(case.tables[0][:steps], 0)
+    lat.step(steps)
+    ra, rb = (t.cpu().numpy() for t in lat.fields(velocity=False))
+    err = max(np.max(np.abs(ra - oa) / oa), np.max(np.abs(rb - ob) / ob))
+    print("256^3 %s: max rel. density error %.2e" % (prec, err))
+    assert err <= tol, err
+    lat.close()
