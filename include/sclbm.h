@@ -96,11 +96,12 @@ typedef struct {
 
 typedef struct sclbm_ctx sclbm_ctx;
 
-/* Bytes of device workspace a context with this configuration needs.
+/* Library infrastructure (not an operation of the paper): bytes of device
+ * workspace a context with this configuration needs.
  * Errors: EINVAL for an invalid configuration. */
 sclbm_status sclbm_workspace_bytes(const sclbm_config *cfg, size_t *bytes);
 
-/* Create a context on the current HIP device.  dev_workspace: device memory of
+/* Library infrastructure: create a context on the current HIP device.  dev_workspace: device memory of
  * at least sclbm_workspace_bytes bytes, 256-byte aligned, owned by the caller and
  * kept alive until sclbm_destroy.  hip_stream: the hipStream_t every call
  * enqueues on (NULL = the null stream).  The populations are undefined until an
@@ -108,7 +109,7 @@ sclbm_status sclbm_workspace_bytes(const sclbm_config *cfg, size_t *bytes);
 sclbm_status sclbm_create(const sclbm_config *cfg, void *dev_workspace, size_t bytes, void *hip_stream,
                           sclbm_ctx **out);
 
-/* Free the host context.  Does not touch device memory. */
+/* Library infrastructure: free the host context.  Does not touch device memory. */
 sclbm_status sclbm_destroy(sclbm_ctx *ctx);
 
 /* Initial state of one box (box = -1: every box): a spherical droplet of A of
@@ -163,15 +164,17 @@ sclbm_status sclbm_set_gradient(sclbm_ctx *ctx, int32_t box, const double A[9]);
  * call at that time (the steps before it are done). */
 sclbm_status sclbm_step(sclbm_ctx *ctx, int64_t nsteps);
 
-/* Advance every box by nsteps through a captured hipGraph of nsteps fused
- * launches (nsteps even and >= 2).  The graph is captured on first use for this
+/* The step of sclbm_step (Sec. 2 Eqs. 6-9, ghost nodes of Sec. 2 Eq. 8 and
+ * Sec. 3 Eq. 14): advance every box by nsteps through a captured hipGraph of
+ * nsteps fused launches (nsteps even and >= 2).  The graph is captured on first use for this
  * nsteps, launch shape and buffer parity, then replayed; the kernels read the
  * time from a device counter, so a replay continues where the last one ended.
  * Same table rules as sclbm_step.  The graph is rebuilt after sclbm_set_launch
  * or when an odd number of eager steps changed the buffer parity. */
 sclbm_status sclbm_step_graph(sclbm_ctx *ctx, int64_t nsteps);
 
-/* Health check of the step calls: every `every` steps (0: off, the default)
+/* A guard the paper does not have (library infrastructure): health check of
+ * the step calls, every `every` steps (0: off, the default)
  * sclbm_step computes every box's FP64 mass and counts the nodes with a NaN/Inf
  * or non-positive density (the same reduction as sclbm_totals) and returns
  * EUNSTABLE naming the first bad box; sclbm_step_graph checks once after each
@@ -179,7 +182,7 @@ sclbm_status sclbm_step_graph(sclbm_ctx *ctx, int64_t nsteps);
  * (every < 0). */
 sclbm_status sclbm_set_health_check(sclbm_ctx *ctx, int64_t every);
 
-/* Current time n. */
+/* Library infrastructure: the current time n (steps taken since the last init or load). */
 sclbm_status sclbm_get_step(const sclbm_ctx *ctx, int64_t *step);
 
 /* Observables of one box at time n into FP64 device arrays: densities rho_a[N],
@@ -207,8 +210,8 @@ sclbm_status sclbm_totals(sclbm_ctx *ctx, int32_t box, double mass[2], double mo
  * synchronise (for time series: collect many, copy once).  Errors: EINVAL. */
 sclbm_status sclbm_droplet_moments(sclbm_ctx *ctx, int32_t box, double *dev_out10);
 
-/* The same 10 moments for every box in one pass, dev_out[nbox][10] (device).
- * Does not synchronise. */
+/* The same 10 moments (droplet inertia tensor for Sec. 2 Eq. 4) for every box
+ * in one pass, dev_out[nbox][10] (device).  Does not synchronise. */
 sclbm_status sclbm_droplet_moments_all(sclbm_ctx *ctx, double *dev_out);
 
 /* sclbm_droplet_moments_all without the workspace's reduction area, for callers
@@ -230,7 +233,8 @@ sclbm_status sclbm_droplet_moments_all_static(sclbm_ctx *ctx, double *dev_out);
 sclbm_status sclbm_droplet_from_moments(const double moments[10], const double center[3], int64_t step,
                                         sclbm_droplet_stats *out);
 
-/* sclbm_droplet_moments + copy + sclbm_droplet_from_moments.  Synchronises. */
+/* Droplet semi-axes and deformation of Sec. 2 Eq. 4 for one box at time n:
+ * sclbm_droplet_moments + copy + sclbm_droplet_from_moments.  Synchronises. */
 sclbm_status sclbm_droplet(sclbm_ctx *ctx, int32_t box, sclbm_droplet_stats *out);
 
 /* Global velocity error E0 of Sec. 4 Eq. 16 for one box at time n against the
@@ -247,12 +251,12 @@ sclbm_status sclbm_velocity_error(sclbm_ctx *ctx, int32_t box, const double A[9]
  * [nbox][2] = {area, volume}, FP64 sums in a fixed order.  Enqueued. */
 sclbm_status sclbm_droplet_surface_all(sclbm_ctx *ctx, double *dev_out);
 
-/* D_LBM from an area and a volume (host arithmetic; area > 0, volume >= 0);
+/* D_LBM of Sec. 5 Eq. 17 from an area and a volume (host arithmetic; area > 0, volume >= 0);
  * Omega_0 = (36 pi V^2)^(1/3).  0 when the area does not exceed Omega_0. */
 sclbm_status sclbm_deformation_lbm(double area, double volume, double *d_lbm);
 
-/* Droplet mass of every box: the sum of rho_A over the nodes with
- * rho_A > rho_B.  dev_out: [nbox] FP64.  Enqueued. */
+/* Droplet mass of every box, the quantity the reinjection of Sec. 2 restores:
+ * the sum of rho_A over the nodes with rho_A > rho_B.  dev_out: [nbox] FP64.  Enqueued. */
 sclbm_status sclbm_droplet_mass_all(sclbm_ctx *ctx, double *dev_out);
 
 /* Mass reinjection (Sec. 2: the ghost-node boundary does not conserve mass,
@@ -266,19 +270,24 @@ sclbm_status sclbm_droplet_mass_all(sclbm_ctx *ctx, double *dev_out);
  * leave the droplet and the mass lands slightly under it.  Synchronises. */
 sclbm_status sclbm_reinject(sclbm_ctx *ctx, int32_t box, const double *target_mass);
 
-/* Checkpoint: bytes needed, save the state (populations of every box, time)
+/* Library infrastructure, checkpoint: bytes needed, save the state (populations of every box, time)
  * into host memory, restore it.  Save synchronises; load is bitwise exact. */
 sclbm_status sclbm_state_bytes(const sclbm_ctx *ctx, size_t *bytes);
 sclbm_status sclbm_save(sclbm_ctx *ctx, void *host_buf, size_t bytes);
 sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
 
-/* Launch shape of the step kernel: a tile of tile_rows rows of tile_waves
- * 64-node columns, (tile_rows, tile_waves) one of (4, 1), (8, 1), (4, 2); and
- * planes per z-chunk (>= 1).  A tile as wide as the box's rows lets every
- * x-shifted store write whole cache lines; the default is (4, 2) for nx > 64,
- * else (8, 1), and (8, 1) also where the last 128-wide tile of a row would be
- * at most half full (nx mod 128 in 1..64).  The default z-chunk minimises
- * (rounds of resident workgroups) x (planes per chunk + 2).  The shape only
+/* Library infrastructure (how the step is launched; no operation of the
+ * paper).  Launch shape of the step kernel: a tile of tile_rows rows of
+ * tile_waves 64-node columns, (tile_rows, tile_waves) one of (4, 1), (8, 1),
+ * (4, 2), and for the 16-bit deviation formats also (4, 4) (256 nodes wide, 16
+ * wavefronts; EINVAL for the other formats); and planes per z-chunk (>= 1).  A
+ * tile as wide as the box's rows lets every x-shifted store write whole cache
+ * lines; the default is (4, 2) for nx > 64, else (8, 1), and (8, 1) also where
+ * the last 128-wide tile of a row would be at most half full (nx mod 128 in
+ * 1..64); the 16-bit formats take (4, 4) where the row's last 256-wide tile is
+ * full or holds more than 160 nodes.  The default z-chunk minimises (rounds of
+ * resident workgroups) x (planes per chunk + 2), at most 32 planes for the
+ * 16-bit formats.  The shape only
  * changes speed, never results.  Pointers of get_launch may be NULL. */
 sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk, int32_t tile_waves);
 sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);
@@ -288,8 +297,9 @@ sclbm_status sclbm_get_launch(const sclbm_ctx *ctx, int32_t *tile_rows, int32_t 
  * NULL.  Errors: EINVAL for an invalid configuration. */
 sclbm_status sclbm_default_launch(const sclbm_config *cfg, int32_t *tile_rows, int32_t *zchunk, int32_t *tile_waves);
 
-/* Autotuner: time trial_steps steps (after one warm-up step) for every tile
- * shape ((4, 1), (8, 1), (4, 2) when nx > 64) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz, and the
+/* Library infrastructure, autotuner: time trial_steps steps (after one warm-up
+ * step) for every tile shape ((4, 1), (8, 1), (4, 2) when nx > 64, (4, 4) for
+ * the 16-bit formats when nx > 128) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz, and the
  * tile's default z-chunk, so the default launch is one of the candidates),
  * keep the fastest and set it.  The output pointers
  * (may be NULL) receive its shape and the best average step time in ms.

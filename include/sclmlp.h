@@ -69,7 +69,8 @@ sclbm_status sclmlp_set_normalization(sclmlp_ctx *ctx, const float in_shift[SCLM
                                       const float in_scale[SCLMLP_NIN], const float out_shift[SCLMLP_NOUT],
                                       const float out_scale[SCLMLP_NOUT]);
 
-/* Inference: dev_windows [n][576] FP32 -> dev_out [n][3] FP32 semi-axes,
+/* Inference: dev_windows [n][576] FP32 -> dev_out [n][3] FP32 semi-axes of the
+ * droplet ellipsoid (Sec. 2 Eq. 4) at each window's last sample,
  * 0 <= n <= max_batch. */
 sclbm_status sclmlp_predict(sclmlp_ctx *ctx, const float *dev_windows, int64_t n, float *dev_out);
 
