@@ -167,6 +167,34 @@ __device__ __forceinline__ void equilibrium_pairs(C ux, C uy, C uz, C r, C aa, C
 constexpr int NXD = 10;
 __host__ __device__ constexpr int xslot_of(int i) { return i < 3 ? i - 1 : i - 5; }
 
+// Directions whose source lies beyond a face: [0] beyond y = 0 (c_y = +1) or
+// z = 0 (c_z = +1), [1] beyond y = ny - 1 or z = nz - 1 (c = -1).
+constexpr int kYin[2][5] = {{3, 7, 10, 15, 17}, {4, 8, 9, 16, 18}};
+constexpr int kZin[2][5] = {{5, 11, 14, 15, 18}, {6, 12, 13, 16, 17}};
+__host__ __device__ constexpr bool face_lists_ok() {
+    for (int f = 0; f < 2; ++f) {
+        const int sg = f ? -1 : 1;
+        int ny = 0, nz = 0;
+        for (int i = 0; i < Q; ++i) {
+            ny += cy_of(i) == sg;
+            nz += cz_of(i) == sg;
+        }
+        if (ny != 5 || nz != 5) return false;
+        for (int m = 0; m < 5; ++m)
+            if (cy_of(kYin[f][m]) != sg || cz_of(kZin[f][m]) != sg) return false;
+    }
+    return true;
+}
+static_assert(face_lists_ok(), "face direction lists");
+// the lists packed five bits per entry, for loops that are not unrolled
+__host__ __device__ constexpr uint32_t pack_dirs(const int (&l)[5]) {
+    uint32_t p = 0;
+    for (int m = 0; m < 5; ++m) p |= uint32_t(l[m]) << (5 * m);
+    return p;
+}
+constexpr uint32_t kYcode[2] = {pack_dirs(kYin[0]), pack_dirs(kYin[1])};
+constexpr uint32_t kZcode[2] = {pack_dirs(kZin[0]), pack_dirs(kZin[1])};
+
 template <int P, int TY, int WX, bool GHOST, int WAVES>
 __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     using S = typename Prec<P>::S;
@@ -197,6 +225,9 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = ly * TXW + lx;
     const int lane = lx & 63, wv = lx >> 6;
+    // wavefront index within the workgroup, uniform (a scalar register)
+    constexpr int NWAVES = TY * WX;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8
     // XCDs by linear id, so give XCD k one contiguous run of tiles, ordered x
     // fastest, then a group of zgroup z-chunks, then y, then the chunk groups,
@@ -492,6 +523,20 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 equilibrium_pairs<C>(ux, uy, uz, r, aa, r3, r45, push);
             }
         }
+        // bracket of the ghost equilibrium g_eq(rho_b, A (x_g - x_c)) = w_i rho_b br of
+        // direction i (known only at run time: the face loops are not unrolled) at
+        // the ghost x_g = (xn, yn, zn) - c_i
+        auto ghost_bracket = [&](int i, int xn, int yn, int zn) -> R {
+            const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
+            const R dxg = (R(xn) - R(a.xc[0])) - R(cx), dyg = (R(yn) - R(a.xc[1])) - R(cy);
+            const R dzg = (R(zn) - R(a.xc[2])) - R(cz);
+            const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
+            const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
+            const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
+            const R cu = R(cx) * gx + R(cy) * gy + R(cz) * gz;
+            const R usq = gx * gx + gy * gy + gz * gz;
+            return R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq;
+        };
         if (GHOST && y < ny) {
             // Populations streaming in from ghost nodes, which hold
             // g_eq(rho_b, A (x_g - x_c)).
@@ -522,29 +567,49 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
                 // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
                 xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = Prec<P>::enc(geq, R(0));
             }
-            // (b) y and z faces (whole rows and planes): each boundary lane writes
-            // the directions whose source lies outside the box in y or z, edges
-            // and corners included.
-            if (valid && (ylo || yhi || zlo || zhi)) {
-                const R dx0 = R(x) - R(a.xc[0]), dy0 = R(y) - R(a.xc[1]), dz0 = R(zc) - R(a.xc[2]);
-                // not unrolled: only rows and planes on a y or z face take this path
+            // (b) y and z faces: the directions whose source lies beyond y = 0, y = ny - 1,
+            // z = 0 or z = nz - 1 (edges included) take the ghost equilibrium at the
+            // face node itself.  On a z-face plane every lane writes its node's five
+            // z directions.
+            if (valid && (zlo || zhi)) {
+                const uint32_t code = zlo ? kZcode[0] : kZcode[1];  // nz >= 3: not both
 #pragma nounroll
-                for (int i = 1; i < Q; ++i) {
-                    const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
-                    const bool from_yz = (cy > 0 && ylo) || (cy < 0 && yhi) || (cz > 0 && zlo) || (cz < 0 && zhi);
-                    if (!from_yz) continue;
-                    const R dxg = dx0 - R(cx), dyg = dy0 - R(cy), dzg = dz0 - R(cz);
-                    const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
-                    const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
-                    const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
-                    const R cu = R(cx) * gx + R(cy) * gy + R(cz) * gz;
-                    const R usq = gx * gx + gy * gy + gz * gz;
-                    const R br = R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq;
+                for (int m = 0; m < 5; ++m) {
+                    const int i = int((code >> (5 * m)) & 31u);
+                    const R br = ghost_bracket(i, x, y, zc);
                     const R wgt = i < 7 ? R(1) / R(18) : R(1) / R(36);
 #pragma unroll
-                    for (int s = 0; s < 2; ++s) {
+                    for (int s = 0; s < 2; ++s)
                         Prec<P>::bstore_bits(rd[s], vo + uint32_t(i) * plane_bytes, 0, Prec<P>::enc(wgt * rhob[s] * br, R(0)));
-                    }
+                }
+            }
+        }
+        if (GHOST) {
+            // A tile holding the row y = 0 or y = ny - 1 writes that row's five y
+            // directions (those also beyond a z face went above) as tasks of one
+            // direction and one 64-node column each, spread over all its wavefronts
+            // (rows beyond the box included), so that the face row's wavefronts do
+            // not hold up the tile's barrier.
+            const bool fy0 = y0 == 0, fy1 = y0 + th == ny;
+            if (fy0 || fy1) {
+                // task t: face t / (5 WX), direction (t / WX) mod 5 of its list, column t mod WX
+#pragma nounroll
+                for (int t = wid; t < 10 * WX; t += NWAVES) {
+                    const int f = t / (5 * WX), m = (t / WX) % 5, c = t % WX;
+                    if (f ? !fy1 : !fy0) continue;
+                    const int i = int(((f ? kYcode[1] : kYcode[0]) >> (5 * m)) & 31u);
+                    const int cz = c_rt(2, i);
+                    if ((cz > 0 && zlo) || (cz < 0 && zhi)) continue;
+                    const int yr = f ? ny - 1 : 0;
+                    const int xn = x0 + 64 * c + lane;
+                    const uint32_t off = xn < x0 + tw ? ((uint32_t(zc) * uint32_t(ny) + uint32_t(yr)) * qnx +
+                                                         uint32_t(i) * uint32_t(nx) + uint32_t(xn)) * EB
+                                                      : kOOB;
+                    const R br = ghost_bracket(i, xn, yr, zc);
+                    const R wgt = i < 7 ? R(1) / R(18) : R(1) / R(36);
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+                        Prec<P>::bstore_bits(rd[s], off, 0, Prec<P>::enc(wgt * rhob[s] * br, R(0)));
                 }
             }
         }
