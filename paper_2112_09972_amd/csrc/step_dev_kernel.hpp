@@ -195,6 +195,8 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = ly * TXW + lx;
     const int lane = lx & 63, wv = lx >> 6;
+    constexpr int NWAVES = TY * WX;
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront in the workgroup
     // tile order: as in k_step (contiguous runs per XCD, z-chunks grouped)
     const uint32_t nbx = gridDim.x, nby = gridDim.y;
     const uint32_t nb = nbx * nby * gridDim.z;
@@ -468,21 +470,57 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
                 const uint32_t other = uint32_t(__shfl_xor(int(bits), 1, 64));  // the pair lane's component
                 if (s == 0) xq[xslot_of(idx)][ly_b][side ? tw + 1 : 0] = bits | (other << 16);
             }
-            // (b) y and z faces (whole rows and planes): each boundary lane writes
-            // the directions whose source lies outside the box in y or z, edges and
-            // corners included, both components as one word.
-            if (valid && (ylo || yhi || zlo || zhi)) {
+            // (b) y and z faces: the directions whose source lies beyond y = 0, y = ny - 1,
+            // z = 0 or z = nz - 1 (edges included) take the ghost equilibrium at the
+            // face node itself, both components as one word.  On a z-face plane every
+            // lane writes its node's five z directions.
+            if (valid && (zlo || zhi)) {
                 const float dx0 = float(x_b) - xcf[0], dy0 = float(y_b) - xcf[1], dz0 = float(zc) - xcf[2];
                 const float4 qr = rmq[sl(0)][ly_b + 1][lx_b + 1];
+                const uint32_t code = zlo ? kZcode[0] : kZcode[1];  // nz >= 3: not both
 #pragma nounroll
-                for (int i = 1; i < Q; ++i) {
+                for (int mz = 0; mz < 5; ++mz) {
+                    const int i = int((code >> (5 * mz)) & 31u);
                     const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
-                    const bool from_yz = (cy > 0 && ylo) || (cy < 0 && yhi) || (cz > 0 && zlo) || (cz < 0 && zhi);
-                    if (!from_yz) continue;
                     const float br = ghost_bracket(A, dx0 - float(cx), dy0 - float(cy), dz0 - float(cz), cx, cy, cz);
                     const uint32_t w = uint32_t(dev_enc<P>(rhob[0] * br, qr.x, qr.y)) |
                                        (uint32_t(dev_enc<P>(rhob[1] * br, qr.z, qr.w)) << 16);
                     __builtin_amdgcn_raw_buffer_store_b32(w, rd, vo + uint32_t(i) * plane_bytes, 0, kStoreNT);
+                }
+            }
+        }
+        if (GHOST) {
+            // A tile holding the row y = 0 or y = ny - 1 writes that row's five y
+            // directions (those also beyond a z face went above) as tasks of one
+            // direction and one 64-node column each, spread over all its wavefronts
+            // (rows beyond the box included), so that the face row's wavefronts do
+            // not hold up the tile's barrier.
+            const bool fy0 = y0 == 0, fy1 = y0 + th == ny;
+            if (fy0 || fy1) {
+                int lane_t = lane;
+                asm volatile("" : "+v"(lane_t));
+                const float *A = gsc, *xcf = gsc + 9;
+                // task t: face t / (5 WX), direction (t / WX) mod 5 of its list, column t mod WX
+#pragma nounroll
+                for (int t = wid; t < 10 * WX; t += NWAVES) {
+                    const int f = t / (5 * WX), my = (t / WX) % 5, c = t % WX;
+                    if (f ? !fy1 : !fy0) continue;
+                    const int i = int(((f ? kYcode[1] : kYcode[0]) >> (5 * my)) & 31u);
+                    const int cx = c_rt(0, i), cy = c_rt(1, i), cz = c_rt(2, i);
+                    if ((cz > 0 && zlo) || (cz < 0 && zhi)) continue;
+                    const int yr = f ? ny - 1 : 0;
+                    const int lxn = 64 * c + lane_t, xn = x0 + lxn;
+                    // the face node's reference densities (in the window; a column beyond
+                    // the tile's nodes reads a cell of the window and stores nothing)
+                    const float4 qr = rmq[sl(0)][yr - y0 + 1][lxn + 1];
+                    const float br = ghost_bracket(A, (float(xn) - xcf[0]) - float(cx), (float(yr) - xcf[1]) - float(cy),
+                                                   (float(zc) - xcf[2]) - float(cz), cx, cy, cz);
+                    const uint32_t w = uint32_t(dev_enc<P>(rhob[0] * br, qr.x, qr.y)) |
+                                       (uint32_t(dev_enc<P>(rhob[1] * br, qr.z, qr.w)) << 16);
+                    const uint32_t off = xn < x0 + tw ? ((uint32_t(zc) * uint32_t(ny) + uint32_t(yr)) * qnx +
+                                                         uint32_t(i) * uint32_t(nx) + uint32_t(xn)) * EB
+                                                      : kOOB;
+                    __builtin_amdgcn_raw_buffer_store_b32(w, rd, off, 0, kStoreNT);
                 }
             }
         }
