@@ -194,7 +194,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
 
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = ly * TXW + lx;
-    const int lane = lx & 63, wv = lx >> 6;
+    const int lane = lx & 63;
     constexpr int NWAVES = TY * WX;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wavefront in the workgroup
     // tile order: as in k_step (contiguous runs per XCD, z-chunks grouped)
@@ -219,7 +219,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
     const int x = x0 + lx, y = y0 + ly;
     const bool valid = (x < a.nx) && (y < a.ny);
     const int tw = min(TXW, a.nx - x0), th = min(TY, a.ny - y0);
-    const int nw = (tw + 63) >> 6;
     const bool left_face = x0 == 0, right_face = x0 + tw == a.nx;
     const bool span = left_face && right_face;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -443,33 +442,9 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
             // The lane's coordinates pass through an empty asm first, so that what this
             // code derives from them is computed here each plane instead of being
             // hoisted out of the march and held in registers (or scratch).
-            int lane_b = lane, x_b = x, y_b = y, lx_b = lx, ly_b = ly;
-            asm volatile("" : "+v"(lane_b), "+v"(x_b), "+v"(y_b), "+v"(lx_b), "+v"(ly_b));
+            int x_b = x, y_b = y, lx_b = lx, ly_b = ly;
+            asm volatile("" : "+v"(x_b), "+v"(y_b), "+v"(lx_b), "+v"(ly_b));
             const float *A = gsc, *xcf = gsc + 9;
-            // (a) Ghosts beside this row at x = -1 and x = nx, into the edge columns of
-            // the x exchange: lanes 0-9 of the first wavefront the left side, lanes
-            // 16-25 of the last the right, lane 2m + s computing component s of
-            // direction m and lane 2m writing the word.
-            const int side = lane_b < 16 ? 0 : 1;
-            const int q = lane_b - 16 * side;
-            if (q < 10 && (side ? (right_face && wv == nw - 1) : (left_face && wv == 0))) {
-                const int sgn = side ? -1 : 1;  // c_x of the incoming directions
-                const int m = q >> 1, s = q & 1;
-                // m = 0..4 -> (c_y, c_z) = (0,0), (1,0), (-1,0), (0,1), (0,-1)
-                const int cyv = m == 1 ? 1 : (m == 2 ? -1 : 0);
-                const int czv = m == 3 ? 1 : (m == 4 ? -1 : 0);
-                const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
-                                        : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
-                const int fx = side ? nx - 1 : 0;  // the receiving face node's x
-                const float br = ghost_bracket(A, float(fx - sgn) - xcf[0], float(y_b) - xcf[1], float(zc) - xcf[2], sgn,
-                                               cyv, czv);
-                // the receiver (fx, y + c_y, z + c_z) lies in the LDS window
-                const float4 qr = rmq[sl(czv)][ly_b + 1 + cyv][fx - x0 + 1];
-                const uint32_t bits =
-                    s ? dev_enc<P>(rhob[1] * br, qr.z, qr.w) : dev_enc<P>(rhob[0] * br, qr.x, qr.y);
-                const uint32_t other = uint32_t(__shfl_xor(int(bits), 1, 64));  // the pair lane's component
-                if (s == 0) xq[xslot_of(idx)][ly_b][side ? tw + 1 : 0] = bits | (other << 16);
-            }
             // (b) y and z faces: the directions whose source lies beyond y = 0, y = ny - 1,
             // z = 0 or z = nz - 1 (edges included) take the ghost equilibrium at the
             // face node itself, both components as one word.  On a z-face plane every
@@ -490,6 +465,42 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
             }
         }
         if (GHOST) {
+            // (a) Ghosts beside the tile's rows at x = -1 and x = nx: their five
+            // populations with c_x pointing into the box stream into the face nodes of
+            // the rows y + c_y, z + c_z, and enter the x exchange at the tile's edge
+            // columns.  The 2 x TY x 10 (side, row, direction, component) values go to
+            // the tile's last wavefronts, entry g = (side TY + row) 10 + 2m + s in
+            // lane g mod 64, so that few wavefronts issue this code; lane pairs (2m,
+            // 2m + 1) share a wavefront, and lane 2m writes the word of both components.
+            {
+                constexpr int NXG = 20 * TY, NXW = (NXG + 63) / 64;
+                static_assert(NXW <= NWAVES, "x-face ghosts need more wavefronts than the tile has");
+                if (wid >= NWAVES - NXW) {
+                    int lane_g = lane;
+                    asm volatile("" : "+v"(lane_g));
+                    const int g = (wid - (NWAVES - NXW)) * 64 + lane_g;
+                    const int side = g / (10 * TY), r = (g / 10) % TY, q = g % 10;
+                    if (g < NXG && r < th && (side ? right_face : left_face)) {
+                        const float *A = gsc, *xcf = gsc + 9;
+                        const int sgn = side ? -1 : 1;  // c_x of the incoming directions
+                        const int m = q >> 1, s = q & 1;
+                        // m = 0..4 -> (c_y, c_z) = (0,0), (1,0), (-1,0), (0,1), (0,-1)
+                        const int cyv = m == 1 ? 1 : (m == 2 ? -1 : 0);
+                        const int czv = m == 3 ? 1 : (m == 4 ? -1 : 0);
+                        const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
+                                                : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
+                        const int fx = side ? nx - 1 : 0;  // the receiving face node's x
+                        const float br = ghost_bracket(A, float(fx - sgn) - xcf[0], float(y0 + r) - xcf[1],
+                                                       float(zc) - xcf[2], sgn, cyv, czv);
+                        // the receiver (fx, y + c_y, z + c_z) lies in the LDS window
+                        const float4 qr = rmq[sl(czv)][r + 1 + cyv][fx - x0 + 1];
+                        const uint32_t bits =
+                            s ? dev_enc<P>(rhob[1] * br, qr.z, qr.w) : dev_enc<P>(rhob[0] * br, qr.x, qr.y);
+                        const uint32_t other = uint32_t(__shfl_xor(int(bits), 1, 64));  // the pair lane's component
+                        if (s == 0) xq[xslot_of(idx)][r][side ? tw + 1 : 0] = bits | (other << 16);
+                    }
+                }
+            }
             // A tile holding the row y = 0 or y = ny - 1 writes that row's five y
             // directions (those also beyond a z face went above) as tasks of one
             // direction and one 64-node column each, spread over all its wavefronts

@@ -224,7 +224,7 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
 
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int tid = ly * TXW + lx;
-    const int lane = lx & 63, wv = lx >> 6;
+    const int lane = lx & 63;
     // wavefront index within the workgroup, uniform (a scalar register)
     constexpr int NWAVES = TY * WX;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -256,7 +256,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     const int x = x0 + lx, y = y0 + ly;
     const bool valid = (x < a.nx) && (y < a.ny);
     const int tw = min(TXW, a.nx - x0), th = min(TY, a.ny - y0);  // valid tile extent
-    const int nw = (tw + 63) >> 6;                                 // wavefronts per row holding nodes
     const bool left_face = x0 == 0, right_face = x0 + tw == a.nx;
     const bool span = left_face && right_face;                     // the tile holds whole rows
     const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -540,33 +539,6 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
         if (GHOST && y < ny) {
             // Populations streaming in from ghost nodes, which hold
             // g_eq(rho_b, A (x_g - x_c)).
-            // (a) Ghosts beside this row at x = -1 and x = nx: their five populations
-            // with c_x pointing into the box stream into the face nodes of the rows
-            // y + c_y, z + c_z, and enter the x exchange at the tile's edge columns.
-            // Lanes 0-9 of the first wavefront do the left side, lanes 16-25 of the
-            // last the right, lane 2m + s taking incoming direction m of component s.
-            const int side = lane < 16 ? 0 : 1;
-            const int q = lane - 16 * side;
-            if (q < 10 && (side ? (right_face && wv == nw - 1) : (left_face && wv == 0))) {
-                const int sgn = side ? -1 : 1;  // c_x of the incoming directions
-                const int m = q >> 1, s = q & 1;
-                // m = 0..4 -> (c_y, c_z) = (0,0), (1,0), (-1,0), (0,1), (0,-1)
-                const int cyv = m == 1 ? 1 : (m == 2 ? -1 : 0);
-                const int czv = m == 3 ? 1 : (m == 4 ? -1 : 0);
-                const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
-                                        : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
-                const int fx = side ? nx - 1 : 0;  // the receiving face node's x
-                const R dxg = R(fx - sgn) - R(a.xc[0]), dyg = R(y) - R(a.xc[1]), dzg = R(zc) - R(a.xc[2]);
-                const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
-                const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
-                const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
-                const R cu = R(sgn) * gx + R(cyv) * gy + R(czv) * gz;
-                const R usq = gx * gx + gy * gy + gz * gz;
-                const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
-                const R geq = wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
-                // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
-                xq[s][xslot_of(idx)][ly][side ? tw + 1 : 0] = Prec<P>::enc(geq, R(0));
-            }
             // (b) y and z faces: the directions whose source lies beyond y = 0, y = ny - 1,
             // z = 0 or z = nz - 1 (edges included) take the ghost equilibrium at the
             // face node itself.  On a z-face plane every lane writes its node's five
@@ -585,6 +557,41 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
             }
         }
         if (GHOST) {
+            // (a) Ghosts beside the tile's rows at x = -1 and x = nx: their five
+            // populations with c_x pointing into the box stream into the face nodes of
+            // the rows y + c_y, z + c_z, and enter the x exchange at the tile's edge
+            // columns.  The 2 x TY x 10 (side, row, direction, component) values go to
+            // the tile's last wavefronts, entry g = (side TY + row) 10 + 2m + s in
+            // lane g mod 64, so that few wavefronts issue this code.
+            {
+                constexpr int NXG = 20 * TY, NXW = (NXG + 63) / 64;
+                static_assert(NXW <= NWAVES, "x-face ghosts need more wavefronts than the tile has");
+                if (wid >= NWAVES - NXW) {
+                    const int g = (wid - (NWAVES - NXW)) * 64 + lane;
+                    const int side = g / (10 * TY), r = (g / 10) % TY, q = g % 10;
+                    if (g < NXG && r < th && (side ? right_face : left_face)) {
+                        const int sgn = side ? -1 : 1;  // c_x of the incoming directions
+                        const int m = q >> 1, s = q & 1;
+                        // m = 0..4 -> (c_y, c_z) = (0,0), (1,0), (-1,0), (0,1), (0,-1)
+                        const int cyv = m == 1 ? 1 : (m == 2 ? -1 : 0);
+                        const int czv = m == 3 ? 1 : (m == 4 ? -1 : 0);
+                        const int idx = sgn > 0 ? (m == 0 ? 1 : m == 1 ? 7 : m == 2 ? 9 : m == 3 ? 11 : 13)
+                                                : (m == 0 ? 2 : m == 1 ? 10 : m == 2 ? 8 : m == 3 ? 14 : 12);
+                        const int fx = side ? nx - 1 : 0;  // the receiving face node's x
+                        const R dxg = R(fx - sgn) - R(a.xc[0]), dyg = R(y0 + r) - R(a.xc[1]), dzg = R(zc) - R(a.xc[2]);
+                        const R gx = Am[0] * dxg + Am[1] * dyg + Am[2] * dzg;
+                        const R gy = Am[3] * dxg + Am[4] * dyg + Am[5] * dzg;
+                        const R gz = Am[6] * dxg + Am[7] * dyg + Am[8] * dzg;
+                        const R cu = R(sgn) * gx + R(cyv) * gy + R(czv) * gz;
+                        const R usq = gx * gx + gy * gy + gz * gz;
+                        const R wgt = m == 0 ? R(1) / R(18) : R(1) / R(36);
+                        const R geq =
+                            wgt * (s ? rhob[1] : rhob[0]) * (R(1) + R(3) * cu + R(4.5) * cu * cu - R(1.5) * usq);
+                        // the receiver (fx, y + c_y, z + c_z) lies in the LDS window (plane slots k-2..k)
+                        xq[s][xslot_of(idx)][r][side ? tw + 1 : 0] = Prec<P>::enc(geq, R(0));
+                    }
+                }
+            }
             // A tile holding the row y = 0 or y = ny - 1 writes that row's five y
             // directions (those also beyond a z face went above) as tasks of one
             // direction and one 64-node column each, spread over all its wavefronts
