@@ -338,6 +338,10 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step_dev(StepArgs a) {
                 rsx = q < th + 2 ? 0 : tw + 1;
                 rsy = q < th + 2 ? q : q - (th + 2);
             }
+            // (an empty asm keeps the ring node's plane-invariant offsets from being
+            // hoisted out of the march: held there, one spilled to scratch in the BF16
+            // build, and its reload waited for every outstanding store)
+            asm volatile("" : "+v"(rsx), "+v"(rsy));
             int gx = x0 - 1 + rsx, gy = y0 - 1 + rsy, gz = z;
             bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
             if (!GHOST) {
