@@ -286,7 +286,7 @@ sclbm_status sclbm_load(sclbm_ctx *ctx, const void *host_buf, size_t bytes);
  * the last 128-wide tile of a row would be at most half full (nx mod 128 in
  * 1..64); the 16-bit formats take (4, 4) where the row's last 256-wide tile is
  * full or holds more than 160 nodes.  The default z-chunk minimises (rounds of
- * resident workgroups) x (planes per chunk + 2), at most 32 planes for the
+ * resident workgroups) x (planes per chunk + 2), at most 64 planes for the
  * 16-bit formats.  The shape only
  * changes speed, never results.  Pointers of get_launch may be NULL. */
 sclbm_status sclbm_set_launch(sclbm_ctx *ctx, int32_t tile_rows, int32_t zchunk, int32_t tile_waves);

@@ -231,14 +231,17 @@ void default_tile(const sclbm_config &c, int &ty, int &wx) {
 // (rounds of resident workgroups) x (planes per chunk + 2): a grid slightly
 // larger than the device would otherwise take a second, nearly empty round
 // (measured: 160^3 at 5.4 GLUPS with 320 workgroups).  The 16-bit formats: four
-// waves per SIMD, and chunks of at most 32 planes (measured at 256^3, FP16 on
-// 128 x 4 tiles, us per step: chunks of 16 / 32 / 64 734 / 735 / 775; the
-// rule's unbounded choice is 64).
+// waves per SIMD, and chunks of at most 64 planes (measured with their default
+// tiles, us per step at the rule's choice capped at 32 / at 64 planes, FP16:
+// 192^3 305-319 / 305, 200^3 352 / 340, 240^3 525 / 506, 256^3 579-583 / 543-547,
+// 288^3 1110-1118 / 1081, 64 boxes of 64^3 548 / 552, 8 boxes of 128^3 571-575 /
+// 554-559; longer chunks lose: 256^3 in one 256-wide tile per row needs 256
+// workgroups of 64 planes to fill the device once).
 int default_zchunk(const sclbm_config &c, int ty, int wx) {
     const long tiles = long((c.nx + 64 * wx - 1) / (64 * wx)) * long((c.ny + ty - 1) / ty) * c.nbox;
     const bool dev = is_dev(c.prec);
     const long resident = (dev ? 1024L * kDevWaves : 2048L) / (ty * wx);
-    const long zmax = dev ? 32 : c.nz;
+    const long zmax = dev ? 64 : c.nz;
     long best_cost = -1, best_zc = std::min<long>(c.nz, zmax);
     for (long nzc = 1; nzc <= std::max(1, c.nz / 2); ++nzc) {
         const long zc = (c.nz + nzc - 1) / nzc;

@@ -119,9 +119,10 @@ def test_empty_droplet():
     (96, 1, 1, (4, 10, 2)),    # 240 workgroups, not 264 (a second, nearly empty round)
     (200, 1, 1, (4, 40, 2)),
     (32, 1, 0, (8, 2, 1)),
-    (256, 1, 2, (4, 32, 4)),   # 16-bit formats: 256-wide tiles, four waves per SIMD, chunks <= 32 planes
-    (200, 1, 3, (4, 20, 4)),   # last 256-wide tile more than 160 nodes
-    (192, 1, 2, (4, 12, 4)),   # a 256-wide tile holds the row: four rows, even where the 128-wide rules take 64 x 8
+    (256, 1, 2, (4, 64, 4)),   # 16-bit formats: 256-wide tiles, four waves per SIMD, chunks <= 64 planes
+    (200, 1, 3, (4, 40, 4)),   # last 256-wide tile more than 160 nodes
+    (192, 1, 2, (4, 39, 4)),   # a 256-wide tile holds the row: four rows, even where the 128-wide rules take 64 x 8
+    (64, 64, 2, (8, 64, 1)),   # 16-bit ensemble of 64^3 boxes: whole-box chunks
     (160, 1, 2, (8, 20, 1)),   # not: 128-wide rules
     (150, 1, 2, (8, 19, 1)),
     (128, 1, 2, (4, 8, 2)),
@@ -132,7 +133,7 @@ def test_default_launch_rules(n, nbox, prec, expect):
     starts with, computed on the host: fill of the last tile, then the chunk
     count that minimises rounds of resident workgroups times planes per chunk
     (16-bit formats: 256-wide tiles where the last one of a row is more than
-    160 nodes long, twice the resident waves, chunks of at most 32 planes)."""
+    160 nodes long, twice the resident waves, chunks of at most 64 planes)."""
     import paper_2112_09972_amd as sc
     assert sc.sclbm_default_launch(cfg(nx=n, ny=n, nz=n, nbox=nbox, prec=prec)) == expect
 

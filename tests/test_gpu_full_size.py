@@ -87,11 +87,11 @@ def oracle_256():
 @pytest.mark.parametrize("prec,tol", [("f16dev", 2e-3), ("bf16dev", 2e-2)])
 def test_256_cubed_deviation_formats(sc, oracle_256, prec, tol):
     """The 256^3 box at the default launch of the 16-bit formats (256 x 4 tiles,
-    32-plane chunks) after 10 steps of its OU drive, on every node."""
+    64-plane chunks) after 10 steps of its OU drive, on every node."""
     case, steps, oa, ob = oracle_256
     lat = sc.Lattice(256, 256, 256, bc="ghost", prec=prec, table_len=steps, g_ab=wl.G_AB, rho_b=case.rho_b,
                      mach_max=wl.MACH_MAX)
-    assert lat.get_launch() == (4, 32, 4)
+    assert lat.get_launch() == (4, 64, 4)
     lat.init_droplet(lat.xc, case.radius, wl.WIDTH, wl.RHO_HI, wl.RHO_LO, case.tables[0][0])
     lat.set_gradient_table(case.tables[0][:steps], 0)
     lat.step(steps)
