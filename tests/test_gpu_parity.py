@@ -489,3 +489,36 @@ def test_moments_where_threads_visit_several_nodes(sc, prec):
     tol = 1e-7 if prec.endswith("dev") else 1e-12
     m, _ = lat.totals()
     assert abs(m[0] - ra.sum()) <= tol * ra.sum() and abs(m[1] - rb.sum()) <= tol * rb.sum()
+
+
+THIN_SHAPES = {"f64": [(4, 2, 1), (8, 3, 1), (4, 5, 2)], "f32": [(4, 2, 1), (8, 3, 1), (4, 5, 2)],
+               "f16dev": [(4, 2, 1), (8, 3, 1), (4, 5, 2), (4, 3, 4)], "bf16dev": [(4, 2, 1), (8, 3, 1), (4, 3, 4)]}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16dev", "bf16dev"])
+@pytest.mark.parametrize("nxyz", [(70, 3, 5), (130, 4, 3), (45, 6, 7), (150, 9, 4)])
+def test_ghost_faces_thin_boxes(sc, prec, nxyz):
+    """The ghost populations of the y and z faces in boxes thin in y and z: one tile
+    holding both y faces (ny = 3, 4, 6 against 4- and 8-row tiles), last tiles of
+    one or two rows, and chunks holding both z faces (nz = 3, 4).  The y-face rows'
+    ghost directions are shared among all wavefronts of a tile, those beyond an x
+    face go to its last wavefronts, including wavefronts whose own rows lie beyond
+    the box; every tile shape against the oracle and bit for bit against the others."""
+    A = np.array([0.0004, 0.0, 0.002, 0.0, -0.0007, 0.0, 0.0011, 0.0, 0.0003])
+    steps = 16
+    tab = np.tile(A, (steps, 1))
+    tol = TOL.get(prec, DEV_TOL.get(prec))
+    out = []
+    for shape in THIN_SHAPES[prec]:
+        lat, o = make_pair(sc, None, nxyz=nxyz, prec=prec, bc="ghost", R=2.0, A=A, steps=steps)
+        lat.set_launch(*shape)
+        lat.set_gradient_table(tab, 0)
+        lat.step(steps)
+        out.append(lat.save())
+        if shape == THIN_SHAPES[prec][0]:
+            o.run(steps, tab)
+            err = rel_density_error(lat, o)
+            print("%s %s: max rel density error %.3e" % (prec, nxyz, err))
+            assert err <= tol
+        lat.close()
+    assert all(np.array_equal(out[0][64:], x[64:]) for x in out[1:])
