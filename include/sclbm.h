@@ -299,8 +299,9 @@ sclbm_status sclbm_default_launch(const sclbm_config *cfg, int32_t *tile_rows, i
 
 /* Library infrastructure, autotuner: time trial_steps steps (after one warm-up
  * step) for every tile shape ((4, 1), (8, 1), (4, 2) when nx > 64, (4, 4) for
- * the 16-bit formats when nx > 128) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz, and the
- * tile's default z-chunk, so the default launch is one of the candidates),
+ * the 16-bit formats when nx > 128) and z-chunk (2, 4, 8, 16, 32, 64, capped at nz, the
+ * tile's default z-chunk, so the default launch is one of the candidates, and
+ * the chunk that puts all workgroups in one round of resident ones, if any),
  * keep the fastest and set it.  The output pointers
  * (may be NULL) receive its shape and the best average step time in ms.
  * The trials overwrite the populations (call it before an init call, or

@@ -466,7 +466,7 @@ class Lattice:
         an init).  Results are cached in $XDG_CACHE_HOME/sclbm/tuning.json keyed
         by device, box shape, boxes, precision and boundary mode."""
         import json
-        key = "%s|%dx%dx%d|%d|%d|%d|rowtiles4" % (self.torch.cuda.get_device_properties(self.device).name, self.nx,
+        key = "%s|%dx%dx%d|%d|%d|%d|rowtiles5" % (self.torch.cuda.get_device_properties(self.device).name, self.nx,
                                                  self.ny, self.nz, self.nbox, self.cfg.prec, self.cfg.bc)
         path = os.path.join(os.environ.get("XDG_CACHE_HOME", os.path.expanduser("~/.cache")), "sclbm", "tuning.json")
         table = {}

@@ -257,6 +257,20 @@ int default_zchunk(const sclbm_config &c, int ty, int wx) {
     return int(best_zc);
 }
 
+// The z-chunk that puts all workgroups of a launch in one round of resident
+// workgroups with as many chunks as fit (0 where even whole-box chunks need more
+// than one round).  An autotuner candidate: single rounds of long chunks beat the
+// rounds rule's split into two rounds for FP32 at some sizes (192^3: 519 against
+// 561 us per step with 64-plane chunks on 64 x 8 tiles; 224^3: 799 against 841 us
+// with 112-plane chunks on 128 x 4 tiles).
+int one_round_zchunk(const sclbm_config &c, int ty, int wx) {
+    const long tiles = long((c.nx + 64 * wx - 1) / (64 * wx)) * long((c.ny + ty - 1) / ty) * c.nbox;
+    const long resident = (is_dev(c.prec) ? 1024L * kDevWaves : 2048L) / (ty * wx);
+    const long nzc = std::min<long>(resident / tiles, c.nz);
+    if (nzc < 1) return 0;
+    return int((c.nz + nzc - 1) / nzc);
+}
+
 // Launch of the step kernel for precision P and a tile of TY rows of WX wavefronts.
 template <int P, int TY, int WX>
 hipError_t launch_step_tile(sclbm_ctx *c, const StepArgs &a) {
@@ -797,8 +811,9 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
     HIP_TRY(hipEventCreate(&ev1));
     float best = -1.0f;
     int bty = ty_keep, bwx = wx_keep, bzc = zc_keep;
-    // candidates: every valid tile with z-chunks 2 .. 64 (capped at nz) and the
-    // tile's default z-chunk, so that the default launch is always among them
+    // candidates: every valid tile with z-chunks 2 .. 64 (capped at nz), the
+    // tile's default z-chunk, so that the default launch is always among them,
+    // and the chunk that fills the device in one round
     const int tys[4] = {4, 8, 4, 4}, wxs[4] = {1, 1, 2, 4};
     const int zcs[6] = {2, 4, 8, 16, 32, 64};
     std::vector<std::array<int, 3>> cand;
@@ -808,6 +823,7 @@ sclbm_status sclbm_autotune(sclbm_ctx *c, int32_t trial_steps, int32_t *tile_row
         std::vector<int> zl;
         for (int zc : zcs) zl.push_back(std::min(zc, c->cfg.nz));
         zl.push_back(default_zchunk(c->cfg, tys[ti], wxs[ti]));
+        if (const int z1 = one_round_zchunk(c->cfg, tys[ti], wxs[ti])) zl.push_back(z1);
         std::sort(zl.begin(), zl.end());
         zl.erase(std::unique(zl.begin(), zl.end()), zl.end());
         for (int zc : zl) cand.push_back({tys[ti], wxs[ti], zc});
