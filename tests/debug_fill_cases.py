@@ -24,6 +24,9 @@ CASES = [
     ("bf16dev", "ghost", (45, 13, 11), (4, 5, 2)), ("f16dev", "ghost", (300, 6, 5), (4, 2, 4)),
     ("bf16dev", "periodic", (257, 6, 5), (4, 3, 4)),
     ("bf16dev", "periodic", (46, 6, 5), (4, 3, 2)),
+    # boxes thin in y and z: both y faces in one tile, tiles with rows beyond the box
+    ("f32", "ghost", (70, 3, 5), (4, 2, 1)), ("f64", "ghost", (45, 6, 7), (4, 5, 2)),
+    ("f16dev", "ghost", (130, 4, 3), (4, 3, 4)), ("bf16dev", "ghost", (150, 9, 4), (8, 3, 1)),
 ]
 
 
