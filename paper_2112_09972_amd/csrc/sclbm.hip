@@ -695,16 +695,13 @@ StepArgs base_args(sclbm_ctx *c) {
     a.nz = c->cfg.nz;
     a.zchunk = c->zchunk;
     a.nzc = (c->cfg.nz + c->zchunk - 1) / c->zchunk;
-    // z-chunks grouped in the tile order: the largest divisor of nzc with
-    // (x tiles) x (group) <= 4 (measured best or within 0.5 % on the 128^3 and
-    // 256^3 boxes, against y-major order and larger groups)
-    {
-        const int ntx = (c->cfg.nx + 64 * c->tile_waves - 1) / (64 * c->tile_waves);
-        int g = 1;
-        for (int d = 1; d <= a.nzc && d * ntx <= 4; ++d)
-            if (a.nzc % d == 0) g = d;
-        a.zgroup = g;
-    }
+    // tile order: x fastest, then y, then z-chunk (groups of one chunk).  Each XCD
+    // then takes a run of neighbouring rows of one chunk, whose ring rows it reads
+    // from its own L2.  Groups of up to 4 / (x tiles) chunks had been best or within
+    // 0.5 % before the ghost faces were balanced; since, single chunks run the 128^3
+    // FP32 box 2.5 % faster (126.4-127.9 against 130.5-130.6 us per launch) and
+    // every other box measured within 0.5 % (96^3 - 320^3, all formats at 256^3).
+    a.zgroup = 1;
     for (int s = 0; s < 2; ++s) {
         a.tau[s] = c->cfg.tau[s];
         a.omega[s] = 1.0 / c->cfg.tau[s];

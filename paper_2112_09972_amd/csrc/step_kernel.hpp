@@ -232,9 +232,11 @@ __global__ __launch_bounds__(64 * WX * TY, WAVES) void k_step(StepArgs a) {
     // XCDs by linear id, so give XCD k one contiguous run of tiles, ordered x
     // fastest, then a group of zgroup z-chunks, then y, then the chunk groups,
     // then box.  Tiles that run at the same time on one XCD then cover a block
-    // of neighbouring rows and chunks: ring rows and, since even chunks march up
-    // in z and odd ones down, the planes at a chunk boundary inside the group are
-    // read by two tiles at about the same time and the second read hits in L2.
+    // of neighbouring rows (and, for groups of several chunks, chunks): their ring
+    // rows hit in that XCD's L2, and since even chunks march up in z and odd ones
+    // down, the planes at a chunk boundary inside a group are read by two tiles at
+    // about the same time.  (The host passes groups of one chunk: measured faster
+    // or equal since the ghost faces were balanced.)
     const uint32_t nbx = gridDim.x, nby = gridDim.y;
     const uint32_t nb = nbx * nby * gridDim.z;
     const uint32_t lin = blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z);
